@@ -1,0 +1,351 @@
+"""Pins of the FP64 oracle against facts other than itself (CPU only).
+
+Each test names what it pins:
+  P1  analytic homogeneous 2-D Green's function + grid refinement (eq. 1-2
+      scaling, source and sampling conventions)
+  P2  discrete reciprocity (symmetry of the variable-density operator)
+  P3  dot-product test of the propagator adjoint
+  P4  dot-product test of the Born/imaging adjoint, and the Born model
+      against finite differences of the forward
+  P5  brute-force finite-difference gradients on every cell (c and rho)
+  P6  explicit-matrix adjoint on a tiny grid
+  P7  density-scale invariance (traces, sum rho g_rho = 0)
+  P8  constant-density reduction to the paper's eq. 2 written with a plain
+      5-point Laplacian
+  P9  absorbing-layer peak damping against the paper's 1.46e6, and the
+      profile's quadratic shape
+  P10 zero residual gives zero misfit and zero gradient
+  P11 linearity in the source and time-shift covariance
+  P12 mirror symmetry
+  P13 checkpointed replay is bitwise store-all
+  P14 stability bound: growth above it, bounded below
+  P15 absorbing-layer efficacy (reflection below -40 dB)
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+from helpers import rel_l2
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _homog(n, nt, h, dt, c=1500.0, rho=1000.0, npml=20, src=None, rcv=None, f0=1e6, cref=1500.0):
+    c_a = np.full((n, n), c, np.float32)
+    r_a = np.full((n, n), rho, np.float32)
+    g = W.Geometry(nx=n, nz=n, nt=nt, h=h, dt=dt, src=np.asarray(src, np.int32),
+                   rcv=np.asarray(rcv, np.int32), npml=npml, pml_cref=cref)
+    w = W.ricker(f0, dt, nt)[None, :]
+    return g, c_a, r_a, w
+
+
+# ------------------------------------------------------------------ P1
+def test_p1_green_function_refinement():
+    """Homogeneous c: traces converge to the analytic 2-D response of a point
+    source q(t) = h^2 w(t)/dt^2 at order 2 under h -> h/2 -> h/4 (dt ~ h)."""
+    c, f0 = 1500.0, 1e6
+    r_phys = 4.5e-3                     # 3 wavelengths
+    half = 9e-3                         # half-width of the interior
+    errs, nums, anas = [], [], []
+    wf = lambda t: (1 - 2 * (math.pi * f0 * (t - 1.5 / f0)) ** 2) * np.exp(-(math.pi * f0 * (t - 1.5 / f0)) ** 2)
+    for lev in range(3):
+        h = 0.1e-3 / 2 ** lev
+        dt = 0.3 * h / c
+        t_end = 6.2e-6
+        nt = int(round(t_end / dt))
+        ni = int(round(half / h))
+        n = 2 * ni + 1 + 2 * 20
+        cen = n // 2
+        off = int(round(r_phys / h))
+        src = [cen * n + cen]
+        rcv = [[cen * n + cen + off]]
+        g, ca, ra, w = _homog(n, nt, h, dt, c=c, src=src, rcv=rcv, f0=f0)
+        num = O.run(g, ca, ra, w, ckpt=2)["traces"][0, :, 0]
+        ana = O.green2d_trace(wf, r_phys, c, h, dt, nt)
+        nums.append(num)
+        anas.append(ana)
+        errs.append(rel_l2(num, ana))
+    orders = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    # Richardson extrapolation of the two finest levels on their common instants:
+    # sample k of level 1 is sample 2k+1 of level 2 (time (k+1) dt_1)
+    k = min(len(nums[1]), (len(nums[2]) - 1) // 2)
+    rich = (4 * nums[2][1:2 * k:2] - nums[1][:k]) / 3
+    e_rich = rel_l2(rich, anas[1][:k])
+    print("errors", errs, "orders", orders, "richardson", e_rich)
+    assert errs[-1] <= 2e-2
+    for o in orders:
+        assert 1.8 <= o <= 2.2
+    assert e_rich <= 2e-3
+
+
+# ------------------------------------------------------------------ P2
+def test_p2_reciprocity():
+    """d(s -> r) gk_s = d(r -> s) gk_r with gk = dt^2 rho c^2 at interior cells."""
+    m = W.small_random_medium(4, 30, 26, 150, n_tx=1, n_rcv=1, npml=4)
+    g = m.geom
+    s = 10 * g.nx + 8
+    r = 17 * g.nx + 21
+    def trace(a, b):
+        g2 = W.Geometry(nx=g.nx, nz=g.nz, nt=g.nt, h=g.h, dt=g.dt, src=np.array([a], np.int32),
+                        rcv=np.array([[b]], np.int32), npml=g.npml, pml_r=g.pml_r, pml_cref=g.pml_cref)
+        return O.run(g2, m.c, m.rho, m.wavelet[:1])["traces"][0, :, 0]
+    gk = lambda x: g.dt ** 2 * float(m.rho.flat[x]) * float(m.c.flat[x]) ** 2
+    a = trace(s, r) * gk(s)
+    b = trace(r, s) * gk(r)
+    assert rel_l2(a, b) <= 1e-12
+    # without the weights the traces differ (the coefficients at s and r differ)
+    assert rel_l2(trace(s, r), trace(r, s)) > 1e-4
+
+
+# ------------------------------------------------------------------ P3
+@pytest.mark.parametrize("ckpt", [0, 3])
+def test_p3_propagator_dot_product(ckpt):
+    m = W.small_random_medium(5, 23, 19, 90, n_tx=3, n_rcv=5, npml=3, dup_receiver=True)
+    g = m.geom
+    rng = np.random.default_rng(1)
+    w = rng.standard_normal((g.n_tx, g.nt))
+    y = rng.standard_normal((g.n_tx, g.nt, g.n_rcv))
+    Fw = O.run(g, m.c, m.rho, w)["traces"]
+    Fty = O.run(g, m.c, m.rho, w, d_adj=y, want_wavelet_grad=True, ckpt=ckpt)["grad_wavelet"]
+    lhs, rhs = np.sum(Fw * y), np.sum(w * Fty)
+    assert abs(lhs - rhs) <= 1e-10 * max(abs(lhs), 1e-300)
+
+
+# ------------------------------------------------------------------ P4
+def test_p4_born_dot_product_and_fd():
+    m = W.small_random_medium(6, 17, 15, 80, n_tx=2, n_rcv=4, npml=2)
+    g = m.geom
+    rng = np.random.default_rng(2)
+    dc = rng.standard_normal(m.c.shape)
+    drho = rng.standard_normal(m.c.shape)
+    y = rng.standard_normal((g.n_tx, g.nt, g.n_rcv))
+    Jdm = O.born(g, m.c, m.rho, m.wavelet, dc, drho)
+    r = O.run(g, m.c, m.rho, m.wavelet, d_adj=y)
+    lhs = np.sum(Jdm * y)
+    rhs = np.sum(dc * r["grad_c"]) + np.sum(drho * r["grad_rho"])
+    assert abs(lhs - rhs) <= 1e-10 * abs(lhs)
+    # the Born model is the derivative of the forward map
+    eps = 1e-3
+    c64, r64 = m.c.astype(np.float64), m.rho.astype(np.float64)
+    tp = O.run(g, c64 + eps * dc, r64 + eps * drho, m.wavelet)["traces"]
+    tm = O.run(g, c64 - eps * dc, r64 - eps * drho, m.wavelet)["traces"]
+    assert rel_l2((tp - tm) / (2 * eps), Jdm) <= 1e-6
+
+
+# ------------------------------------------------------------------ P5
+@pytest.mark.parametrize("seed,nx,nz,nt,npml", [(1, 9, 8, 60, 2), (2, 12, 10, 90, 3)])
+def test_p5_brute_force_gradient(seed, nx, nz, nt, npml):
+    m = W.small_random_medium(seed, nx, nz, nt, n_tx=2, n_rcv=4, npml=npml, dup_receiver=True)
+    g = m.geom
+    rng = np.random.default_rng(seed + 100)
+    c_obs = (m.c * (1 + 0.02 * (rng.random(m.c.shape) - 0.5))).astype(np.float64)
+    obs = O.run(g, c_obs, m.rho, m.wavelet)["traces"]
+    r = O.run(g, m.c, m.rho, m.wavelet, d_obs=obs)
+    c0, r0 = m.c.astype(np.float64), m.rho.astype(np.float64)
+    J = lambda cc, rr: O.run(g, cc, rr, m.wavelet, d_obs=obs, gradient=False)["misfit"]
+    gc = np.zeros_like(c0)
+    gr = np.zeros_like(c0)
+    eps = 1e-3
+    for iz in range(g.nz):
+        for ix in range(g.nx):
+            e = np.zeros_like(c0); e[iz, ix] = eps
+            gc[iz, ix] = (J(c0 + e, r0) - J(c0 - e, r0)) / (2 * eps)
+            gr[iz, ix] = (J(c0, r0 + e) - J(c0, r0 - e)) / (2 * eps)
+    assert rel_l2(r["grad_c"], gc) <= 1e-6
+    assert rel_l2(r["grad_rho"], gr) <= 1e-6
+
+
+# ------------------------------------------------------------------ P6
+def test_p6_explicit_matrix_adjoint():
+    """Matrix of w -> traces by unit impulses; the adjoint routine's matrix
+    (unit adjoint sources -> dJ/dw) is its transpose."""
+    m = W.small_random_medium(8, 6, 5, 8, n_tx=1, n_rcv=3, npml=1)
+    g = m.geom
+    T, R = g.nt, g.n_rcv
+    F = np.zeros((T * R, T))
+    for k in range(T):
+        w = np.zeros((1, T)); w[0, k] = 1.0
+        F[:, k] = O.run(g, m.c, m.rho, w)["traces"].reshape(-1)
+    Ft = np.zeros((T, T * R))
+    w0 = np.zeros((1, T))
+    for k in range(T * R):
+        y = np.zeros((1, T, R)); y.reshape(-1)[k] = 1.0
+        Ft[:, k] = O.run(g, m.c, m.rho, w0, d_adj=y, want_wavelet_grad=True)["grad_wavelet"][0]
+    assert np.max(np.abs(Ft - F.T)) <= 1e-13 * max(np.max(np.abs(F)), 1.0)
+    assert np.max(np.abs(F)) > 0
+
+
+# ------------------------------------------------------------------ P7
+def test_p7_density_scale_invariance():
+    m = W.small_random_medium(9, 20, 18, 100, n_tx=2, n_rcv=4, npml=3)
+    g = m.geom
+    a = O.run(g, m.c, m.rho, m.wavelet)["traces"]
+    b = O.run(g, m.c, m.rho.astype(np.float64) * 1.7, m.wavelet)["traces"]
+    assert rel_l2(b, a) <= 1e-13
+    obs = O.run(g, m.c.astype(np.float64) * 1.01, m.rho, m.wavelet)["traces"]
+    r = O.run(g, m.c, m.rho, m.wavelet, d_obs=obs)
+    s = np.sum(m.rho.astype(np.float64) * r["grad_rho"])
+    assert abs(s) <= 1e-12 * np.linalg.norm(m.rho) * np.linalg.norm(r["grad_rho"])
+
+
+# ------------------------------------------------------------------ P8
+def test_p8_constant_density_is_eq2():
+    """With constant rho the flux form equals eq. 2 written directly:
+    U[t] = (2 - D^2 dt^2)/(1 + D dt) U[t-1] + (D dt - 1)/(1 + D dt) U[t-2]
+           + C^2 dt^2/(1 + D dt) (Lap_5pt U[t-1]) + S[t]  (zero-padded Laplacian)."""
+    m = W.small_random_medium(10, 25, 21, 120, n_tx=1, n_rcv=6, npml=4, rho_contrast=0.0)
+    g = m.geom
+    m.rho[:] = 1000.0
+    ref = O.run(g, m.c, m.rho, m.wavelet)["traces"][0]
+    D = O.damping(g.nx, g.nz, g.npml, O.dmax(g.pml_cref, g.pml_r, g.npml, g.h))
+    C = m.c.astype(np.float64)
+    dt, h = g.dt, g.h
+    den = 1 + D * dt
+    u1 = np.zeros((g.nz, g.nx)); u2 = np.zeros((g.nz, g.nx))
+    out = np.zeros((g.nt, g.n_rcv))
+    sz, sx = divmod(int(g.src[0]), g.nx)
+    for t in range(g.nt):
+        p = np.pad(u1, 1)
+        lap = (p[1:-1, :-2] + p[1:-1, 2:] + p[:-2, 1:-1] + p[2:, 1:-1] - 4 * u1) / h ** 2
+        u0 = (2 - D ** 2 * dt ** 2) / den * u1 + (D * dt - 1) / den * u2 + C ** 2 * dt ** 2 / den * lap
+        u0[sz, sx] += float(m.wavelet[0, t])
+        out[t] = u0.reshape(-1)[g.rcv[0]]
+        u2, u1 = u1, u0
+    assert rel_l2(out, ref) <= 1e-12
+
+
+# ------------------------------------------------------------------ P9
+def test_p9_absorbing_layer_constant():
+    gold = json.load(open(os.path.join(GOLD, "paper_constants.json")))
+    N = gold["pml_cells"]
+    h = gold["domain_m"] / gold["grid_cells"]
+    dm = O.dmax(1500.0, gold["pml_target_attenuation"], N, h)
+    sig = gold["pml_dmax_significant_figures"]
+    assert float(f"{dm:.{sig}g}") == gold["pml_dmax_outer"]
+    D = O.damping(60, 50, N, dm)
+    # outermost cell carries D_max, the inner edge 0, quadratic in between, D = Dx + Dz
+    assert D[25, 0] == pytest.approx(dm, rel=1e-15)
+    assert D[25, N] == 0.0 and D[25, 59 - N] == 0.0
+    assert D[25, N - 1] == pytest.approx(dm / N ** 2, rel=1e-13)
+    assert D[25, 10] == pytest.approx(dm * ((N - 10) / N) ** 2, rel=1e-13)
+    assert D[0, 0] == pytest.approx(2 * dm, rel=1e-15)
+    assert D[49, 59] == pytest.approx(2 * dm, rel=1e-15)
+
+
+def test_p9b_paper_grid_recipe():
+    """The paper's simulation set-up is self-consistent: 10 cm at lambda/8 for
+    350 kHz in water gives ~188 cells; 1034 samples of 90.243 ns last 93.31 us."""
+    gold = json.load(open(os.path.join(GOLD, "paper_constants.json")))
+    lam = 1500.0 / gold["center_frequency_hz"]
+    n = gold["domain_m"] / (lam * gold["grid_spacing_wavelengths"])
+    assert abs(n - gold["grid_cells"]) / gold["grid_cells"] < 0.02
+    dur = gold["source_samples"] * gold["source_sample_interval_s"]
+    assert dur == pytest.approx(gold["source_duration_s"], rel=1e-4)
+
+
+# ------------------------------------------------------------------ P10
+def test_p10_zero_residual():
+    m = W.small_random_medium(11, 16, 14, 70, n_tx=2, n_rcv=3, npml=2)
+    g = m.geom
+    obs = O.run(g, m.c, m.rho, m.wavelet)["traces"]
+    r = O.run(g, m.c, m.rho, m.wavelet, d_obs=obs)
+    assert r["misfit"] == 0.0
+    assert not np.any(r["grad_c"]) and not np.any(r["grad_rho"])
+
+
+# ------------------------------------------------------------------ P11
+def test_p11_linearity_and_time_shift():
+    m = W.small_random_medium(12, 18, 16, 90, n_tx=1, n_rcv=4, npml=3)
+    g = m.geom
+    w = m.wavelet.astype(np.float64)
+    a = O.run(g, m.c, m.rho, w)["traces"]
+    # a power-of-two scale commutes exactly with every rounding: bitwise
+    b = O.run(g, m.c, m.rho, 4.0 * w)["traces"]
+    assert np.array_equal(b, 4.0 * a)
+    b = O.run(g, m.c, m.rho, 2.5 * w)["traces"]
+    assert rel_l2(b, 2.5 * a) <= 1e-14
+    k = 7
+    ws = np.zeros_like(w); ws[:, k:] = w[:, :-k]
+    c = O.run(g, m.c, m.rho, ws)["traces"]
+    assert np.array_equal(c[:, k:], a[:, :-k])
+    assert np.all(c[:, :k] == 0)
+
+
+# ------------------------------------------------------------------ P12
+def test_p12_mirror_symmetry():
+    """A medium symmetric under ix -> nx-1-ix with the source on the axis gives
+    mirrored traces at mirrored receivers."""
+    m = W.small_random_medium(13, 21, 18, 120, n_tx=1, n_rcv=2, npml=3)
+    g = m.geom
+    m.c[:] = 0.5 * (m.c + m.c[:, ::-1])
+    m.rho[:] = 0.5 * (m.rho + m.rho[:, ::-1])
+    g.src[0] = 5 * g.nx + 10
+    g.rcv[0, 0] = 12 * g.nx + 3
+    g.rcv[0, 1] = 12 * g.nx + (g.nx - 1 - 3)
+    tr = O.run(g, m.c, m.rho, m.wavelet)["traces"][0]
+    assert rel_l2(tr[:, 1], tr[:, 0]) <= 1e-13
+    # and the up/down direction is not symmetric (sanity)
+    g.rcv[0, 1] = (g.nz - 1 - 12) * g.nx + 3
+    tr2 = O.run(g, m.c, m.rho, m.wavelet)["traces"][0]
+    assert rel_l2(tr2[:, 1], tr2[:, 0]) > 1e-3
+
+
+# ------------------------------------------------------------------ P13
+@pytest.mark.parametrize("K", [1, 2, 7, 33])
+def test_p13_checkpoint_bitwise(K):
+    m = W.small_random_medium(14, 15, 13, 66, n_tx=2, n_rcv=3, npml=2)
+    g = m.geom
+    obs = O.run(g, m.c.astype(np.float64) * 1.01, m.rho, m.wavelet)["traces"]
+    a = O.run(g, m.c, m.rho, m.wavelet, d_obs=obs, ckpt=0, want_wavelet_grad=True)
+    b = O.run(g, m.c, m.rho, m.wavelet, d_obs=obs, ckpt=K, want_wavelet_grad=True)
+    for k in ("traces", "grad_c", "grad_rho", "grad_wavelet"):
+        assert np.array_equal(a[k], b[k]), k
+    assert a["misfit"] == b["misfit"]
+
+
+# ------------------------------------------------------------------ P14
+def test_p14_stability_bound():
+    """Homogeneous, no damping: Courant 0.70 stays bounded, 0.72 (> 1/sqrt 2) grows."""
+    n = 41
+    amps = []
+    for cr in (0.70, 0.72):
+        h = 1e-3
+        dt = cr * h / 1500.0
+        g, ca, ra, w = _homog(n, 1500, h, dt, npml=0, src=[20 * n + 20], rcv=[[20 * n + 25]],
+                              f0=1.0 / (20 * dt))
+        tr = O.run(g, ca, ra, w)["traces"][0, :, 0]
+        amps.append(np.max(np.abs(tr[-100:])))
+    assert np.isfinite(amps[0]) and amps[0] < 10.0
+    assert not np.isfinite(amps[1]) or amps[1] > 1e6
+
+
+# ------------------------------------------------------------------ P15
+def test_p15_absorbing_layer_efficacy():
+    """The 20-cell quadratic layer (R = 1e-3) cuts the boundary reflection to
+    below -30 dB of the direct arrival, and by more than 25 dB against the
+    same grid with the damping switched off (R -> 1).  Reflection = difference
+    to a grid so large that no reflection reaches the receiver in the window."""
+    h, c, f0 = 0.1e-3, 1500.0, 1.5e6
+    dt = 0.3 * h / c
+    nt = 900
+
+    def run(ni, pml_r):
+        n = ni + 2 * 20
+        cen = n // 2
+        g, ca, ra, w = _homog(n, nt, h, dt, c=c, src=[cen * n + cen], rcv=[[cen * n + cen + 25]], f0=f0)
+        g.pml_r = pml_r
+        return O.run(g, ca, ra, w)["traces"][0, :, 0]
+
+    big = run(81 + 2 * 140, 1e-3)
+    direct = np.max(np.abs(big))
+    db = {}
+    for r in (1e-3, 1 - 1e-12):
+        db[r] = 20 * math.log10(np.max(np.abs(run(81, r) - big)) / direct)
+    print("reflection dB (layer, no damping)", db)
+    assert db[1e-3] < -30.0
+    assert db[1e-3] < db[1 - 1e-12] - 25.0
