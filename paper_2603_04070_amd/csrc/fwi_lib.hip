@@ -1,0 +1,759 @@
+// Host side of the FWI-gradient library: C ABI declared in include/fwi.h.
+//
+// A plan turns media + geometry into work items (medium, group of G
+// transmits), lays out one caller-provided workspace, builds the per-tile
+// receiver tables, and enqueues the step kernels of fwi_kernels.hpp.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "fwi.h"
+#include "fwi_kernels.hpp"
+
+using namespace fwi;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+struct ItemPlan {
+    int medium;
+    int tx0, g_used;
+    int K, J;
+    int tiles_x, tiles_z, n_tiles;
+    int blk0;                  // first block of this item in the block table
+    int steps;                 // schedule length 2T + K(J-1)
+    size_t seg_off, ck_off, lam_off, acc_off;   // workspace byte offsets
+    size_t src_off, tile_off_off, entry_off;    // plan-table byte offsets
+};
+
+struct MediumPlan {
+    fwi_grid g;
+    std::vector<int32_t> src, rcv;
+    double dmax;
+    int item0, item1;
+    int acc_slots;
+    size_t coef_off, acc_off;  // workspace
+    size_t ex_off, ez_off;     // plan tables
+};
+
+}  // namespace
+
+struct fwi_plan {
+    fwi_dtype dtype = FWI_F32;
+    fwi_options opt{};
+    int G = 1, rows = 4;
+    bool acc_double = false;
+    size_t tsize = 4, asize = 4;
+    std::vector<MediumPlan> media;
+    std::vector<ItemPlan> items;
+    std::vector<int2> blocks;
+    int max_steps = 0, max_fwd = 0, max_adj = 0;
+    int64_t cell_updates = 0, recompute_updates = 0;
+
+    // workspace layout
+    size_t ws_bytes = 0;
+    size_t zero_off = 0, zero_bytes = 0;
+    size_t clear_off = 0, clear_bytes = 0;       // accumulators + lambda planes (+ zero plane)
+    size_t lam_region_off = 0, lam_region_bytes = 0;
+    size_t acc_region_off = 0, acc_region_bytes = 0;
+    size_t partial_off = 0;
+
+    // plan-owned device tables
+    void* d_tables = nullptr;
+    size_t tables_bytes = 0;
+    int2* d_blocks = nullptr;
+    void* d_items = nullptr;        // Item<T, Acc>[n_items]
+    void* d_media = nullptr;        // MediumDev<T>[n_media]
+    unsigned* d_status = nullptr;
+    void* h_stage = nullptr;        // pinned staging for items + media descriptors
+    size_t item_bytes = 0, media_bytes = 0;
+    hipEvent_t stage_ev = nullptr;
+    bool stage_pending = false;
+    hipStream_t last_stream = nullptr;
+    bool have_call = false;
+
+    // forward -> adjoint state
+    const void* fwd_ws = nullptr;
+
+    // hipGraph replay of the batched gradient
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    const void* graph_ws = nullptr;
+    unsigned graph_flags = 0;
+
+    std::string last_error;
+};
+
+namespace {
+
+fwi_status fail(fwi_plan* p, fwi_status st, const std::string& msg)
+{
+    if (p) p->last_error = msg;
+    return st;
+}
+
+#define HIPCHK(plan, call)                                                                   \
+    do {                                                                                     \
+        hipError_t e_ = (call);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return fail(plan, FWI_ERR_HIP, std::string(#call " failed: ") + hipGetErrorString(e_)); \
+    } while (0)
+
+double dmax_of(const fwi_grid& g)
+{
+    if (g.npml <= 0) return 0.0;
+    return 3.0 * g.pml_cref * std::log(1.0 / g.pml_r) / (2.0 * g.npml * g.h);
+}
+
+double prof(int i, int n, int N, double dmax)
+{
+    if (i < N) { double r = (double)(N - i) / N; return dmax * r * r; }
+    if (i > n - 1 - N) { double r = (double)(i - (n - 1 - N)) / N; return dmax * r * r; }
+    return 0.0;
+}
+
+// Host-side validation of one grid (no HIP call).
+fwi_status validate_grid(const fwi_grid& g, int idx, std::string& msg)
+{
+    char buf[256];
+    auto bad = [&](fwi_status st, const char* what) {
+        std::snprintf(buf, sizeof buf, "medium %d: %s", idx, what);
+        msg = buf;
+        return st;
+    };
+    if (g.npml < 0) return bad(FWI_ERR_INVALID, "npml < 0");
+    if (g.nx < 2 * g.npml + 3 || g.nz < 2 * g.npml + 3) return bad(FWI_ERR_INVALID, "nx, nz must be >= 2*npml+3");
+    if (g.nt < 1) return bad(FWI_ERR_INVALID, "nt < 1");
+    if (!(g.h > 0) || !(g.dt > 0) || !std::isfinite(g.h) || !std::isfinite(g.dt))
+        return bad(FWI_ERR_INVALID, "h and dt must be positive");
+    if (g.npml > 0 && (!(g.pml_r > 0) || !(g.pml_r < 1) || !(g.pml_cref > 0)))
+        return bad(FWI_ERR_INVALID, "pml_r must be in (0,1) and pml_cref > 0");
+    if (!(g.c_max > 0) || !std::isfinite(g.c_max)) return bad(FWI_ERR_INVALID, "c_max must be positive");
+    if (g.n_tx < 1 || g.n_rcv < 1) return bad(FWI_ERR_INVALID, "n_tx and n_rcv must be >= 1");
+    if (!g.src || !g.rcv) return bad(FWI_ERR_INVALID, "src and rcv must be host arrays");
+    const int64_t ncell = (int64_t)g.nx * g.nz;
+    if (ncell * 4 > INT32_MAX) return bad(FWI_ERR_INVALID, "grid too large (nx*nz*4 must fit int32)");
+    if ((int64_t)g.n_tx * g.nt * g.n_rcv > INT32_MAX) return bad(FWI_ERR_INVALID, "n_tx*nt*n_rcv too large");
+    for (int p = 0; p < g.n_tx; ++p) {
+        if (g.src[p] < 0 || g.src[p] >= ncell) return bad(FWI_ERR_GEOMETRY, "source cell outside the grid");
+        for (int r = 0; r < g.n_rcv; ++r) {
+            const int32_t c = g.rcv[(int64_t)p * g.n_rcv + r];
+            if (c < 0 || c >= ncell) return bad(FWI_ERR_GEOMETRY, "receiver cell outside the grid");
+        }
+    }
+    // frozen-coefficient stability of the damped leapfrog update:
+    // (D dt)^2 + c^2 dt^2 * 8/h^2 < 4 with D = 2 D_max in the corners
+    const double e = 2.0 * dmax_of(g) * g.dt, cr = g.c_max * g.dt / g.h;
+    if (e * e + 8.0 * cr * cr >= 4.0) return bad(FWI_ERR_CFL, "unstable: 4 (Dmax dt)^2 + 8 (c_max dt/h)^2 >= 4");
+    return FWI_OK;
+}
+
+// Kernel table per (dtype, accumulator, G).
+template <typename T, typename Acc, int G>
+void launch_step(dim3 grid, hipStream_t st, const void* items, const int2* blocks, int s, int mode, int rows)
+{
+    hipLaunchKernelGGL((step_kernel<T, G, Acc>), grid, dim3(kTileX, kWavesZ), 0, st,
+                       reinterpret_cast<const Item<T, Acc>*>(items), blocks, s, mode, rows);
+}
+
+template <typename T, typename Acc>
+void launch_step_g(int G, dim3 grid, hipStream_t st, const void* items, const int2* blocks, int s, int mode, int rows)
+{
+    if (G == 1) launch_step<T, Acc, 1>(grid, st, items, blocks, s, mode, rows);
+    else if (G == 2) launch_step<T, Acc, 2>(grid, st, items, blocks, s, mode, rows);
+    else launch_step<T, Acc, 4>(grid, st, items, blocks, s, mode, rows);
+}
+
+void step(fwi_plan* p, dim3 grid, hipStream_t st, const int2* blocks, int s, int mode)
+{
+    if (p->dtype == FWI_F64)
+        launch_step_g<double, double>(p->G, grid, st, p->d_items, blocks, s, mode, p->rows);
+    else if (p->acc_double)
+        launch_step_g<float, double>(p->G, grid, st, p->d_items, blocks, s, mode, p->rows);
+    else
+        launch_step_g<float, float>(p->G, grid, st, p->d_items, blocks, s, mode, p->rows);
+}
+
+int grid_for(int64_t n, int per_block, int cap)
+{
+    int64_t b = (n + per_block - 1) / per_block;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(b, cap));
+}
+
+// Zero a byte range of the workspace (multiple of 4 bytes, 4-byte aligned).
+void zero_bytes(hipStream_t st, void* base, size_t bytes)
+{
+    if (!bytes) return;
+    const int64_t n = (int64_t)(bytes / 4);
+    hipLaunchKernelGGL(zero_kernel<uint32_t>, dim3(grid_for(n, 256, 8192)), dim3(256), 0, st,
+                       reinterpret_cast<uint32_t*>(base), n);
+}
+
+}  // namespace
+
+// ----------------------------------------------------------------------------- plan creation
+
+extern "C" const char* fwi_last_create_error(void) { return g_create_error.c_str(); }
+
+extern "C" const char* fwi_status_string(fwi_status s)
+{
+    switch (s) {
+    case FWI_OK: return "ok";
+    case FWI_ERR_INVALID: return "invalid argument";
+    case FWI_ERR_CFL: return "time step violates the stability bound";
+    case FWI_ERR_GEOMETRY: return "source or receiver outside the grid";
+    case FWI_ERR_NOMEM: return "out of device memory";
+    case FWI_ERR_WORKSPACE: return "workspace missing or too small";
+    case FWI_ERR_HIP: return "HIP runtime error";
+    case FWI_ERR_NONFINITE: return "non-finite result";
+    case FWI_ERR_MEDIUM: return "invalid medium values (c or rho not positive and finite)";
+    case FWI_ERR_STATE: return "adjoint called without a preceding forward";
+    }
+    return "unknown status";
+}
+
+extern "C" const char* fwi_plan_last_error(const fwi_plan* p) { return p ? p->last_error.c_str() : ""; }
+
+static fwi_status create_impl(fwi_plan* p, fwi_dtype dtype, const fwi_grid* grids, int32_t n_media,
+                              const fwi_options* opt)
+{
+    // ---------------- host validation (no HIP calls before this passes)
+    if (!grids || n_media < 1) return fail(p, FWI_ERR_INVALID, "grids must be non-NULL and n_media >= 1");
+    if (dtype != FWI_F32 && dtype != FWI_F64) return fail(p, FWI_ERR_INVALID, "unknown dtype");
+    fwi_options o{};
+    o.mode = FWI_BATCHED;
+    if (opt) o = *opt;
+    if (o.mode != FWI_PLAIN && o.mode != FWI_BATCHED) return fail(p, FWI_ERR_INVALID, "unknown mode");
+    if (o.group != 0 && o.group != 1 && o.group != 2 && o.group != 4)
+        return fail(p, FWI_ERR_INVALID, "group must be 0, 1, 2 or 4");
+    if (o.mode == FWI_PLAIN && o.group > 1) return fail(p, FWI_ERR_INVALID, "plain mode runs one transmit per item");
+    if (o.rows < 0 || o.rows > 64) return fail(p, FWI_ERR_INVALID, "rows must be in [0, 64]");
+    if (o.ckpt_interval < 0) return fail(p, FWI_ERR_INVALID, "ckpt_interval must be >= 0");
+    if (o.mem_budget < 0) return fail(p, FWI_ERR_INVALID, "mem_budget must be >= 0");
+    if (o.use_graph && o.mode != FWI_BATCHED) return fail(p, FWI_ERR_INVALID, "use_graph requires FWI_BATCHED");
+    for (int i = 0; i < n_media; ++i) {
+        std::string msg;
+        fwi_status st = validate_grid(grids[i], i, msg);
+        if (st != FWI_OK) return fail(p, st, msg);
+    }
+
+    p->dtype = dtype;
+    p->opt = o;
+    p->G = o.group ? o.group : (o.mode == FWI_PLAIN ? 1 : 4);
+    p->rows = o.rows ? o.rows : 4;
+    p->acc_double = dtype == FWI_F64 || o.acc_double;
+    p->tsize = dtype == FWI_F64 ? 8 : 4;
+    p->asize = p->acc_double ? 8 : 4;
+    const int G = p->G, rows = p->rows;
+    const int tile_rows = kWavesZ * rows;
+
+    // ---------------- media and items
+    p->media.resize(n_media);
+    for (int i = 0; i < n_media; ++i) {
+        MediumPlan& m = p->media[i];
+        m.g = grids[i];
+        m.src.assign(grids[i].src, grids[i].src + grids[i].n_tx);
+        m.rcv.assign(grids[i].rcv, grids[i].rcv + (size_t)grids[i].n_tx * grids[i].n_rcv);
+        m.g.src = nullptr;
+        m.g.rcv = nullptr;
+        m.dmax = dmax_of(m.g);
+        m.item0 = (int)p->items.size();
+        for (int tx = 0; tx < m.g.n_tx; tx += G) {
+            ItemPlan it{};
+            it.medium = i;
+            it.tx0 = tx;
+            it.g_used = std::min(G, m.g.n_tx - tx);
+            it.tiles_x = (m.g.nx + kTileX - 1) / kTileX;
+            it.tiles_z = (m.g.nz + tile_rows - 1) / tile_rows;
+            it.n_tiles = it.tiles_x * it.tiles_z;
+            p->items.push_back(it);
+        }
+        m.item1 = (int)p->items.size();
+        m.acc_slots = o.mode == FWI_PLAIN ? 1 : (m.item1 - m.item0);
+        p->cell_updates += 2LL * m.g.nx * m.g.nz * m.g.nt * m.g.n_tx;
+    }
+
+    // ---------------- checkpoint intervals under the memory budget
+    double budget = o.mem_budget;
+    if (budget <= 0) {
+        size_t fr = 0, tot = 0;
+        HIPCHK(p, hipMemGetInfo(&fr, &tot));
+        budget = 0.6 * (double)fr;
+    }
+    auto plane_bytes = [&](const ItemPlan& it) {
+        const MediumPlan& m = p->media[it.medium];
+        return align_up((size_t)m.g.nx * m.g.nz * G * p->tsize);
+    };
+    auto state_bytes = [&](const ItemPlan& it, int K) {
+        const int T = p->media[it.medium].g.nt;
+        const int J = (T + K - 1) / K;
+        return plane_bytes(it) * (size_t)(K + 2 * (J - 1) + 2);
+    };
+    auto auto_k = [&](int T) {
+        if (T <= 2) return T;
+        int K = (int)std::lround(std::sqrt(2.0 * T));
+        return std::max(2, std::min(K, T));
+    };
+    for (auto& it : p->items) {
+        const int T = p->media[it.medium].g.nt;
+        int K;
+        if (o.ckpt_interval == 0) K = auto_k(T);
+        else if (o.ckpt_interval >= T) K = T;
+        else K = std::max(2, o.ckpt_interval);
+        if (T == 1) K = 1;
+        it.K = std::min(K, T);
+    }
+    if (o.ckpt_interval == 0) {
+        // keep every plane for as many items as the budget allows
+        double used = 0;
+        for (auto& m : p->media) used += 2.0 * m.g.nx * m.g.nz * p->tsize + 2.0 * m.acc_slots * m.g.nx * m.g.nz * p->asize;
+        if (o.mode == FWI_PLAIN) {
+            size_t mx_all = 0;
+            for (auto& it : p->items) mx_all = std::max(mx_all, state_bytes(it, p->media[it.medium].g.nt));
+            if (used + mx_all <= budget)
+                for (auto& it : p->items) it.K = p->media[it.medium].g.nt;
+        } else {
+            for (auto& it : p->items) used += state_bytes(it, it.K);
+            std::vector<int> order(p->items.size());
+            for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+            std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+                return state_bytes(p->items[a], p->media[p->items[a].medium].g.nt) <
+                       state_bytes(p->items[b], p->media[p->items[b].medium].g.nt);
+            });
+            for (int i : order) {
+                ItemPlan& it = p->items[i];
+                const int T = p->media[it.medium].g.nt;
+                const double extra = (double)state_bytes(it, T) - (double)state_bytes(it, it.K);
+                if (used + extra <= budget) { used += extra; it.K = T; }
+            }
+        }
+    }
+    for (auto& it : p->items) {
+        const int T = p->media[it.medium].g.nt;
+        it.J = (T + it.K - 1) / it.K;
+        it.steps = 2 * T + it.K * (it.J - 1);
+        p->max_steps = std::max(p->max_steps, it.steps);
+        p->max_fwd = std::max(p->max_fwd, T);
+        p->max_adj = std::max(p->max_adj, it.steps - T);
+        const MediumPlan& m = p->media[it.medium];
+        p->recompute_updates += (int64_t)it.K * (it.J - 1) * m.g.nx * m.g.nz * it.g_used;
+    }
+
+    // ---------------- workspace layout:
+    // [zero plane][accumulators][lambda planes][misfit partials][coefficients][checkpoints][segments]
+    size_t off = 0;
+    size_t zmax = 0;
+    for (auto& it : p->items) zmax = std::max(zmax, plane_bytes(it));
+    p->zero_off = off; p->zero_bytes = zmax; off += zmax;
+    p->acc_region_off = off;
+    for (auto& m : p->media) {
+        m.acc_off = off;
+        off += align_up((size_t)m.acc_slots * 2 * m.g.nx * m.g.nz * p->asize);
+    }
+    p->acc_region_bytes = off - p->acc_region_off;
+    p->lam_region_off = off;
+    if (o.mode == FWI_PLAIN) {
+        size_t mx = 0;
+        for (auto& it : p->items) mx = std::max(mx, plane_bytes(it));
+        for (auto& it : p->items) it.lam_off = off;
+        off += 2 * mx;
+    } else {
+        for (auto& it : p->items) { it.lam_off = off; off += 2 * plane_bytes(it); }
+    }
+    p->lam_region_bytes = off - p->lam_region_off;
+    p->clear_off = p->zero_off;
+    p->clear_bytes = off - p->zero_off;
+    p->partial_off = off;
+    off += align_up((size_t)n_media * kMisfitBlocks * sizeof(double));
+    for (auto& m : p->media) { m.coef_off = off; off += align_up((size_t)2 * m.g.nx * m.g.nz * p->tsize); }
+    if (o.mode == FWI_PLAIN) {
+        size_t mx_ck = 0, mx_seg = 0;
+        for (auto& it : p->items) {
+            mx_ck = std::max(mx_ck, plane_bytes(it) * 2 * (size_t)(it.J - 1));
+            mx_seg = std::max(mx_seg, plane_bytes(it) * (size_t)it.K);
+        }
+        for (auto& it : p->items) { it.ck_off = off; }
+        off += mx_ck;
+        for (auto& it : p->items) { it.seg_off = off; }
+        off += mx_seg;
+    } else {
+        for (auto& it : p->items) { it.ck_off = off; off += plane_bytes(it) * 2 * (size_t)(it.J - 1); }
+        for (auto& it : p->items) { it.seg_off = off; off += plane_bytes(it) * (size_t)it.K; }
+    }
+    p->ws_bytes = off;
+    for (auto& it : p->items) {
+        const MediumPlan& m = p->media[it.medium];
+        it.acc_off = m.acc_off + (o.mode == FWI_PLAIN ? 0 : (size_t)(&it - &p->items[m.item0]) * 2 * m.g.nx * m.g.nz * p->asize);
+    }
+
+    // ---------------- plan tables: profiles, sources, per-tile receiver entries, blocks
+    std::vector<unsigned char> tab;
+    auto tab_put = [&](const void* src, size_t bytes) {
+        size_t o2 = align_up(tab.size());
+        tab.resize(o2 + align_up(bytes));
+        if (bytes) std::memcpy(tab.data() + o2, src, bytes);
+        return o2;
+    };
+    for (auto& m : p->media) {
+        std::vector<double> ex(m.g.nx), ez(m.g.nz);
+        for (int i = 0; i < m.g.nx; ++i) ex[i] = prof(i, m.g.nx, m.g.npml, m.dmax) * m.g.dt;
+        for (int i = 0; i < m.g.nz; ++i) ez[i] = prof(i, m.g.nz, m.g.npml, m.dmax) * m.g.dt;
+        if (dtype == FWI_F64) {
+            m.ex_off = tab_put(ex.data(), ex.size() * 8);
+            m.ez_off = tab_put(ez.data(), ez.size() * 8);
+        } else {
+            std::vector<float> fx(ex.begin(), ex.end()), fz(ez.begin(), ez.end());
+            m.ex_off = tab_put(fx.data(), fx.size() * 4);
+            m.ez_off = tab_put(fz.data(), fz.size() * 4);
+        }
+    }
+    for (auto& it : p->items) {
+        const MediumPlan& m = p->media[it.medium];
+        std::vector<int32_t> src(G, -1);
+        for (int g = 0; g < it.g_used; ++g) src[g] = m.src[it.tx0 + g];
+        it.src_off = tab_put(src.data(), src.size() * 4);
+        // receiver entries grouped by tile, sorted by slot within a tile
+        struct Raw { int tile; int32_t slot; int32_t trace_off; int order; };
+        std::vector<Raw> raw;
+        for (int g = 0; g < it.g_used; ++g) {
+            const int tx = it.tx0 + g;
+            for (int r = 0; r < m.g.n_rcv; ++r) {
+                const int32_t cell = m.rcv[(size_t)tx * m.g.n_rcv + r];
+                const int ix = cell % m.g.nx, iz = cell / m.g.nx;
+                const int tile = (iz / tile_rows) * it.tiles_x + ix / kTileX;
+                raw.push_back({tile, cell * G + g, (int32_t)((int64_t)tx * m.g.nt * m.g.n_rcv + r), (int)raw.size()});
+            }
+        }
+        std::stable_sort(raw.begin(), raw.end(), [](const Raw& a, const Raw& b) {
+            return a.tile != b.tile ? a.tile < b.tile : (a.slot != b.slot ? a.slot < b.slot : a.order < b.order);
+        });
+        std::vector<int32_t> toff(it.n_tiles + 1, 0);
+        std::vector<Entry> ent(raw.size());
+        for (size_t k = 0; k < raw.size(); ++k) {
+            toff[raw[k].tile + 1]++;
+            ent[k] = {raw[k].slot, raw[k].trace_off, 0, 0};
+        }
+        for (int t = 0; t < it.n_tiles; ++t) toff[t + 1] += toff[t];
+        for (size_t k = 0; k < ent.size();) {
+            size_t e = k;
+            while (e < ent.size() && raw[e].tile == raw[k].tile && ent[e].slot == ent[k].slot) ++e;
+            ent[k].run = (int32_t)(e - k);
+            k = e;
+        }
+        it.tile_off_off = tab_put(toff.data(), toff.size() * 4);
+        it.entry_off = tab_put(ent.data(), ent.size() * sizeof(Entry));
+    }
+    for (size_t i = 0; i < p->items.size(); ++i) {
+        ItemPlan& it = p->items[i];
+        it.blk0 = (int)p->blocks.size();
+        for (int t = 0; t < it.n_tiles; ++t) p->blocks.push_back(make_int2((int)i, t));
+    }
+    const size_t blocks_off = tab_put(p->blocks.data(), p->blocks.size() * sizeof(int2));
+    p->item_bytes = (p->dtype == FWI_F64 ? sizeof(Item<double, double>)
+                     : p->acc_double ? sizeof(Item<float, double>) : sizeof(Item<float, float>)) * p->items.size();
+    p->media_bytes = (p->dtype == FWI_F64 ? sizeof(MediumDev<double>) : sizeof(MediumDev<float>)) * p->media.size();
+    const size_t items_off = align_up(tab.size());
+    const size_t media_off = align_up(items_off + p->item_bytes);
+    const size_t status_off = align_up(media_off + p->media_bytes);
+    p->tables_bytes = status_off + kAlign;
+    tab.resize(p->tables_bytes, 0);
+
+    HIPCHK(p, hipMalloc(&p->d_tables, p->tables_bytes));
+    HIPCHK(p, hipMemcpy(p->d_tables, tab.data(), p->tables_bytes, hipMemcpyHostToDevice));
+    auto* base = reinterpret_cast<unsigned char*>(p->d_tables);
+    p->d_blocks = reinterpret_cast<int2*>(base + blocks_off);
+    p->d_items = base + items_off;
+    p->d_media = base + media_off;
+    p->d_status = reinterpret_cast<unsigned*>(base + status_off);
+    HIPCHK(p, hipHostMalloc(&p->h_stage, align_up(p->item_bytes) + align_up(p->media_bytes), hipHostMallocDefault));
+    HIPCHK(p, hipEventCreateWithFlags(&p->stage_ev, hipEventDisableTiming));
+    return FWI_OK;
+}
+
+extern "C" fwi_status fwi_plan_create(fwi_plan** out, fwi_dtype dtype, const fwi_grid* grids, int32_t n_media,
+                                      const fwi_options* opt)
+{
+    g_create_error.clear();
+    if (!out) { g_create_error = "out must be non-NULL"; return FWI_ERR_INVALID; }
+    *out = nullptr;
+    fwi_plan* p = new (std::nothrow) fwi_plan();
+    if (!p) { g_create_error = "host allocation failed"; return FWI_ERR_NOMEM; }
+    fwi_status st = create_impl(p, dtype, grids, n_media, opt);
+    if (st != FWI_OK) {
+        g_create_error = p->last_error;
+        fwi_plan_destroy(p);
+        return st;
+    }
+    *out = p;
+    return FWI_OK;
+}
+
+extern "C" void fwi_plan_destroy(fwi_plan* p)
+{
+    if (!p) return;
+    if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
+    if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
+    if (p->stage_ev) (void)hipEventDestroy(p->stage_ev);
+    if (p->h_stage) (void)hipHostFree(p->h_stage);
+    if (p->d_tables) (void)hipFree(p->d_tables);
+    delete p;
+}
+
+extern "C" fwi_status fwi_plan_workspace_size(const fwi_plan* p, size_t* bytes)
+{
+    if (!p || !bytes) return FWI_ERR_INVALID;
+    *bytes = p->ws_bytes;
+    return FWI_OK;
+}
+
+extern "C" fwi_status fwi_plan_get_info(const fwi_plan* p, fwi_plan_info* info)
+{
+    if (!p || !info) return FWI_ERR_INVALID;
+    std::memset(info, 0, sizeof *info);
+    info->cell_updates = p->cell_updates;
+    info->recompute_updates = p->recompute_updates;
+    info->workspace_bytes = (int64_t)p->ws_bytes;
+    info->n_items = (int32_t)p->items.size();
+    info->group = p->G;
+    info->rows = p->rows;
+    if (p->opt.mode == FWI_PLAIN) {
+        int64_t l = 0;
+        for (auto& it : p->items) l += it.steps;
+        info->launches = (int32_t)std::min<int64_t>(l, INT32_MAX);
+    } else {
+        info->launches = p->max_steps;
+    }
+    info->max_ckpt = 0;
+    info->min_ckpt = INT32_MAX;
+    for (auto& it : p->items) {
+        info->max_ckpt = std::max(info->max_ckpt, it.K);
+        info->min_ckpt = std::min(info->min_ckpt, it.K);
+    }
+    return FWI_OK;
+}
+
+// ----------------------------------------------------------------------------- calls
+
+namespace {
+
+enum Call { kExecute = 0, kForward = 1, kAdjoint = 2 };
+
+template <typename T, typename Acc>
+void fill_descriptors(fwi_plan* p, const fwi_io* io, unsigned char* ws, bool adj_from_dadj)
+{
+    auto* items = reinterpret_cast<Item<T, Acc>*>(p->h_stage);
+    auto* media = reinterpret_cast<MediumDev<T>*>(reinterpret_cast<unsigned char*>(p->h_stage) + align_up(p->item_bytes));
+    auto* tabs = reinterpret_cast<unsigned char*>(p->d_tables);
+    for (size_t i = 0; i < p->items.size(); ++i) {
+        const ItemPlan& ip = p->items[i];
+        const MediumPlan& m = p->media[ip.medium];
+        const fwi_io& mio = io[ip.medium];
+        Item<T, Acc> d{};
+        d.nx = m.g.nx; d.nz = m.g.nz; d.nt = m.g.nt; d.g_used = ip.g_used;
+        d.K = ip.K; d.J = ip.J; d.tiles_x = ip.tiles_x; d.n_tiles = ip.n_tiles;
+        d.n_rcv = m.g.n_rcv; d.tx0 = ip.tx0;
+        d.inject_adj = adj_from_dadj ? 1 : 0;
+        d.sample = 1;
+        d.plane = (int64_t)m.g.nx * m.g.nz * p->G;
+        d.wavelet_stride = mio.wavelet_shared ? 0 : m.g.nt;
+        d.coef = reinterpret_cast<const T*>(ws + m.coef_off);
+        d.ex = reinterpret_cast<const T*>(tabs + m.ex_off);
+        d.ez = reinterpret_cast<const T*>(tabs + m.ez_off);
+        d.seg = reinterpret_cast<T*>(ws + ip.seg_off);
+        d.ck = reinterpret_cast<T*>(ws + ip.ck_off);
+        d.lam = reinterpret_cast<T*>(ws + ip.lam_off);
+        d.acc = reinterpret_cast<Acc*>(ws + ip.acc_off);
+        d.zero = reinterpret_cast<const T*>(ws + p->zero_off);
+        d.wavelet = reinterpret_cast<const T*>(mio.wavelet);
+        d.src = reinterpret_cast<const int32_t*>(tabs + ip.src_off);
+        d.traces = reinterpret_cast<T*>(mio.traces);
+        d.d_obs = reinterpret_cast<const T*>(mio.d_obs);
+        d.d_adj = reinterpret_cast<const T*>(mio.d_adj);
+        d.tile_off = reinterpret_cast<const int32_t*>(tabs + ip.tile_off_off);
+        d.entries = reinterpret_cast<const Entry*>(tabs + ip.entry_off);
+        items[i] = d;
+    }
+    for (size_t i = 0; i < p->media.size(); ++i) {
+        const MediumPlan& m = p->media[i];
+        const fwi_io& mio = io[i];
+        MediumDev<T> d{};
+        d.nx = m.g.nx; d.nz = m.g.nz; d.item0 = m.item0; d.item1 = m.item1;
+        d.n_tx = m.g.n_tx; d.nt = m.g.nt; d.n_rcv = m.g.n_rcv;
+        d.h = m.g.h; d.dt = m.g.dt; d.dmax = m.dmax; d.c_max = m.g.c_max;
+        d.npml = m.g.npml;
+        d.acc_stride = 2LL * m.g.nx * m.g.nz;
+        d.c = reinterpret_cast<const T*>(mio.c);
+        d.rho = reinterpret_cast<const T*>(mio.rho);
+        d.coef = reinterpret_cast<T*>(ws + m.coef_off);
+        d.traces = reinterpret_cast<const T*>(mio.traces);
+        d.d_obs = reinterpret_cast<const T*>(mio.d_obs);
+        d.grad_c = reinterpret_cast<T*>(mio.grad_c);
+        d.grad_rho = reinterpret_cast<T*>(mio.grad_rho);
+        d.misfit = mio.misfit;
+        d.acc0 = ws + m.acc_off;
+        d.acc_slots = m.acc_slots;
+        media[i] = d;
+    }
+}
+
+template <typename T, typename Acc>
+void enqueue_medium(fwi_plan* p, hipStream_t st, int which, unsigned char* ws)
+{
+    const int nm = (int)p->media.size();
+    int64_t nmax = 0;
+    for (auto& m : p->media) nmax = std::max<int64_t>(nmax, (int64_t)m.g.nx * m.g.nz);
+    const auto* md = reinterpret_cast<const MediumDev<T>*>(p->d_media);
+    const dim3 g2(grid_for(nmax, 256, 2048), nm);
+    if (which == 0) {
+        hipLaunchKernelGGL(prep_kernel<T>, g2, dim3(256), 0, st, md, p->d_status);
+    } else if (which == 1) {
+        double* partial = reinterpret_cast<double*>(ws + p->partial_off);
+        hipLaunchKernelGGL(misfit_partial_kernel<T>, dim3(kMisfitBlocks, nm), dim3(256), 0, st, md, partial);
+        hipLaunchKernelGGL(misfit_final_kernel<T>, dim3((nm + 63) / 64), dim3(64), 0, st, md, nm,
+                           (const double*)partial, p->d_status);
+    } else {
+        hipLaunchKernelGGL((finalize_kernel<T, Acc>), g2, dim3(256), 0, st, md, p->d_status);
+    }
+}
+
+void medium_kernels(fwi_plan* p, hipStream_t st, int which, unsigned char* ws)
+{
+    if (p->dtype == FWI_F64) enqueue_medium<double, double>(p, st, which, ws);
+    else if (p->acc_double) enqueue_medium<float, double>(p, st, which, ws);
+    else enqueue_medium<float, float>(p, st, which, ws);
+}
+
+// The whole launch sequence of one call on stream st (no host synchronisation).
+void enqueue_sequence(fwi_plan* p, hipStream_t st, unsigned char* ws, int call, bool want_grad)
+{
+    hipLaunchKernelGGL(zero_kernel<unsigned>, dim3(1), dim3(64), 0, st, p->d_status, (int64_t)1);
+    if (call != kAdjoint) {
+        zero_bytes(st, ws + p->clear_off, p->clear_bytes);
+        medium_kernels(p, st, 0, ws);
+    } else {
+        zero_bytes(st, ws + p->acc_region_off, p->acc_region_bytes);
+        zero_bytes(st, ws + p->lam_region_off, p->lam_region_bytes);
+    }
+    // an execute without gradient outputs is a forward solve (+ misfit)
+    if (call == kExecute && !want_grad) call = kForward;
+    const int mode = call == kExecute ? kRunAll : call == kForward ? kRunFwdOnly : kRunAdjOnly;
+    if (p->opt.mode == FWI_BATCHED) {
+        const int S = call == kExecute ? p->max_steps : call == kForward ? p->max_fwd : p->max_adj;
+        const dim3 grid((unsigned)p->blocks.size());
+        for (int s = 0; s < S; ++s) step(p, grid, st, p->d_blocks, s, mode);
+    } else {
+        for (size_t i = 0; i < p->items.size(); ++i) {
+            const ItemPlan& it = p->items[i];
+            const int T = p->media[it.medium].g.nt;
+            const int S = call == kExecute ? it.steps : call == kForward ? T : it.steps - T;
+            if (call != kForward && i > 0) zero_bytes(st, ws + it.lam_off, p->lam_region_bytes);
+            for (int s = 0; s < S; ++s) step(p, dim3(it.n_tiles), st, p->d_blocks + it.blk0, s, mode);
+        }
+    }
+    if (call != kAdjoint) medium_kernels(p, st, 1, ws);
+    if (call != kForward) medium_kernels(p, st, 2, ws);
+}
+
+fwi_status run_call(fwi_plan* p, const fwi_io* io, void* workspace, size_t bytes, void* stream, int call)
+{
+    if (!p) return FWI_ERR_INVALID;
+    p->last_error.clear();
+    if (!io) return fail(p, FWI_ERR_INVALID, "io must be non-NULL");
+    if (!workspace || bytes < p->ws_bytes) return fail(p, FWI_ERR_WORKSPACE, "workspace missing or too small");
+    if ((reinterpret_cast<uintptr_t>(workspace) & (kAlign - 1)) != 0)
+        return fail(p, FWI_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+    bool want_grad = false, dadj = false;
+    for (size_t i = 0; i < p->media.size(); ++i) {
+        const fwi_io& m = io[i];
+        if (!m.c || !m.rho || !m.wavelet || !m.traces) return fail(p, FWI_ERR_INVALID, "c, rho, wavelet and traces are required");
+        const bool g = m.grad_c || m.grad_rho;
+        want_grad |= g;
+        if (call == kExecute && g && !m.d_obs) return fail(p, FWI_ERR_INVALID, "a gradient needs d_obs");
+        if (call == kAdjoint) {
+            if (!m.d_adj && !m.d_obs) return fail(p, FWI_ERR_INVALID, "adjoint needs d_adj or d_obs");
+            if (i == 0) dadj = m.d_adj != nullptr;
+            else if (dadj != (m.d_adj != nullptr)) return fail(p, FWI_ERR_INVALID, "d_adj must be given for all media or none");
+        }
+    }
+    if (call == kAdjoint && p->fwd_ws != workspace) return fail(p, FWI_ERR_STATE, "no forward state in this workspace");
+    if (call != kExecute && p->opt.mode == FWI_PLAIN && p->items.size() > 1)
+        return fail(p, FWI_ERR_INVALID, "plain mode keeps one transmit's state: forward/adjoint need FWI_BATCHED");
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    unsigned char* ws = reinterpret_cast<unsigned char*>(workspace);
+
+    // descriptors: reuse the pinned staging buffer once the previous upload has been consumed
+    if (p->stage_pending) HIPCHK(p, hipEventSynchronize(p->stage_ev));
+    if (p->dtype == FWI_F64) fill_descriptors<double, double>(p, io, ws, dadj);
+    else if (p->acc_double) fill_descriptors<float, double>(p, io, ws, dadj);
+    else fill_descriptors<float, float>(p, io, ws, dadj);
+    HIPCHK(p, hipMemcpyAsync(p->d_items, p->h_stage, align_up(p->item_bytes) + p->media_bytes,
+                             hipMemcpyHostToDevice, st));
+    HIPCHK(p, hipEventRecord(p->stage_ev, st));
+    p->stage_pending = true;
+
+    const bool graph = p->opt.use_graph && call == kExecute;
+    if (graph) {
+        const unsigned flags = want_grad ? 1u : 0u;
+        if (!p->gexec || p->graph_ws != workspace || p->graph_flags != flags) {
+            if (p->gexec) { (void)hipGraphExecDestroy(p->gexec); p->gexec = nullptr; }
+            if (!p->cap_stream) HIPCHK(p, hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
+            hipGraph_t gr = nullptr;
+            HIPCHK(p, hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
+            enqueue_sequence(p, p->cap_stream, ws, call, want_grad);
+            HIPCHK(p, hipStreamEndCapture(p->cap_stream, &gr));
+            hipError_t e = hipGraphInstantiate(&p->gexec, gr, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(gr);
+            if (e != hipSuccess) return fail(p, FWI_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+            p->graph_ws = workspace;
+            p->graph_flags = flags;
+        }
+        HIPCHK(p, hipGraphLaunch(p->gexec, st));
+    } else {
+        enqueue_sequence(p, st, ws, call, want_grad);
+    }
+    HIPCHK(p, hipGetLastError());
+    p->last_stream = st;
+    p->have_call = true;
+    p->fwd_ws = (call == kForward || (call == kExecute && !want_grad)) ? workspace : nullptr;
+    return FWI_OK;
+}
+
+}  // namespace
+
+extern "C" fwi_status fwi_plan_execute(fwi_plan* p, const fwi_io* io, void* ws, size_t bytes, void* stream)
+{
+    return run_call(p, io, ws, bytes, stream, kExecute);
+}
+
+extern "C" fwi_status fwi_plan_forward(fwi_plan* p, const fwi_io* io, void* ws, size_t bytes, void* stream)
+{
+    return run_call(p, io, ws, bytes, stream, kForward);
+}
+
+extern "C" fwi_status fwi_plan_adjoint(fwi_plan* p, const fwi_io* io, void* ws, size_t bytes, void* stream)
+{
+    return run_call(p, io, ws, bytes, stream, kAdjoint);
+}
+
+extern "C" fwi_status fwi_plan_check(fwi_plan* p)
+{
+    if (!p) return FWI_ERR_INVALID;
+    if (!p->have_call) return FWI_OK;
+    HIPCHK(p, hipStreamSynchronize(p->last_stream));
+    unsigned flags = 0;
+    HIPCHK(p, hipMemcpy(&flags, p->d_status, sizeof flags, hipMemcpyDeviceToHost));
+    if (flags & kFlagMedium) return fail(p, FWI_ERR_MEDIUM, "c or rho not positive and finite");
+    if (flags & kFlagCfl) return fail(p, FWI_ERR_CFL, "a cell's c exceeds the declared c_max");
+    if (flags & kFlagNonfinite) return fail(p, FWI_ERR_NONFINITE, "non-finite misfit or gradient");
+    return FWI_OK;
+}
