@@ -1,0 +1,278 @@
+"""Benchmark of the FWI-gradient hot path on one MI355X.
+
+One step = one gradient of every medium of the workload: forward solve of
+every transmit, misfit, adjoint with imaging, finalisation (the whole path).
+Default workload: 64 media of uneven size (side U{256..768}, 8-32 transmits,
+2000-5000 steps, h 0.1 mm, dt 20 ns, rod + Gaussian media, FP32), run by the
+batched form.  The plain form (one transmit and one step per launch) is timed
+beside it on the first media of the same workload.
+
+Prints one JSON line.  Inputs are synthetic and resident in HBM before the
+timed region; observed traces come from the forward solve of partner media.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "FWI gradient Gcell-updates/s (fwd+adj), % HBM roofline; batched vs plain"
+HBM_PEAK_GBS = 8000.0          # MI355X published HBM3E bandwidth
+BYTES_PER_UPDATE = 24          # algorithmic bytes per cell-update (48 per forward+adjoint pair)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="uneven64", choices=["uneven64", "rodgauss512", "disc128"])
+    ap.add_argument("--media", type=int, default=64, help="media of the uneven workload")
+    ap.add_argument("--nt", type=int, default=0, help="override every medium's step count (counter runs)")
+    ap.add_argument("--mode", default="batched", choices=["batched", "plain"])
+    ap.add_argument("--group", type=int, default=0)
+    ap.add_argument("--rows", type=int, default=0)
+    ap.add_argument("--ckpt", type=int, default=0)
+    ap.add_argument("--graph", type=int, default=0)
+    ap.add_argument("--plain-media", type=int, default=1, help="media of the workload timed in plain form (0: skip)")
+    ap.add_argument("--cpu-baseline", type=int, default=1)
+    ap.add_argument("--cpu-steps", type=int, default=0, help="oracle sample steps (0: sized for ~15 s)")
+    ap.add_argument("--copy-calibration", type=int, default=0,
+                    help="MiB of one device-to-device copy run first (reference for HBM byte counters)")
+    return ap.parse_args()
+
+
+def build_workload(name, n_media):
+    import workloads as W
+    if name == "uneven64":
+        media = W.c4_batch(40, n_media=n_media)
+        desc = (f"uneven{n_media}: {n_media} rod+Gaussian media, side U{{256..768}}, 8-32 transmits, "
+                "2000-5000 steps, h 0.1 mm, dt 20 ns, 2.5 MHz Ricker, linear array pitch 0.3 mm")
+    elif name == "rodgauss512":
+        media = [W.c2_medium(20)]
+        desc = "rodgauss512: 512^2, h 0.1 mm, dt 20 ns, 4000 steps, 128 elements, 16 transmits, 2.5 MHz Ricker"
+    else:
+        media = [W.c1_small()]
+        desc = "disc128: 128^2, h 0.2 mm, dt 20 ns, 1000 steps, 32 elements, 1 transmit, 1 MHz Ricker"
+    partners = [W.partner_medium(m, 7000 + i) for i, m in enumerate(media)]
+    return media, partners, desc
+
+
+def to_dev(media, dtype, dev):
+    import numpy as np
+    import torch
+    npd = np.float64 if dtype == "f64" else np.float32
+    out = []
+    for m in media:
+        t = lambda a: torch.from_numpy(np.ascontiguousarray(a, npd)).to(dev)
+        out.append({"c": t(m.c), "rho": t(m.rho), "wavelet": t(m.wavelet)})
+    return out
+
+
+def make_plan(media, dtype, mode, args, c_max):
+    import paper_2603_04070_amd as F
+    grids = [F.GridSpec.of(m.geom, c_max) for m in media]
+    return F.Plan(grids, dtype=dtype, mode=mode, ckpt=args.ckpt, group=args.group if mode == "batched" else 0,
+                  rows=args.rows, use_graph=bool(args.graph) and mode == "batched")
+
+
+def observed(partners, dtype, args, c_max, dev):
+    """Observed traces: forward solve of the partner media (batched form)."""
+    import torch
+    import paper_2603_04070_amd as F
+    plan = make_plan(partners, dtype, "batched", args, c_max)
+    ios = to_dev(partners, dtype, dev)
+    outs = F.forward(plan, ios)
+    del plan
+    return [o["traces"] for o in outs]
+
+
+def time_gradient(plan, media_dev, d_obs, dtype, steps, warmup, dev):
+    import torch
+    td = torch.float64 if dtype == "f64" else torch.float32
+    ios = []
+    for g, m, o in zip(plan.grids, media_dev, d_obs):
+        io = dict(m)
+        io["d_obs"] = o
+        io["traces"] = torch.empty((g.n_tx, g.nt, g.n_rcv), dtype=td, device=dev)
+        io["grad_c"] = torch.empty((g.nz, g.nx), dtype=td, device=dev)
+        io["grad_rho"] = torch.empty((g.nz, g.nx), dtype=td, device=dev)
+        io["misfit"] = torch.zeros(1, dtype=torch.float64, device=dev)
+        ios.append(io)
+    ws = plan.new_workspace(dev)
+    for _ in range(warmup):
+        plan.execute(ios, ws)
+    plan.check()
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(steps):
+        plan.execute(ios, ws, stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    plan.check()
+    ms = e0.elapsed_time(e1) / steps
+    return ms, ios
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build measures the single-GPU hot path "
+              "(multi-GPU sharding is described, not run)", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    import paper_2603_04070_amd as F
+
+    dev = torch.device("cuda:0")
+    if args.copy_calibration > 0:
+        n = args.copy_calibration * 2 ** 20 // 4
+        a = torch.ones(n, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+    dtype = "f64" if args.workload == "disc128" else "f32"
+    media, partners, desc = build_workload(args.workload, args.media)
+    if args.nt > 0:
+        for m in media + partners:
+            m.geom.nt = args.nt
+            m.wavelet = m.wavelet[:, :args.nt]
+        desc += f" [steps overridden to {args.nt}]"
+    c_max = 1.02 * max(float(np.max(m.c)) for m in media + partners)
+    d_obs = observed(partners, dtype, args, c_max, dev)
+    mdev = to_dev(media, dtype, dev)
+
+    plan = make_plan(media, dtype, args.mode, args, c_max)
+    info = plan.info
+    ms, _ = time_gradient(plan, mdev, d_obs, dtype, args.steps, args.warmup, dev)
+    updates = info["cell_updates"]
+    value = updates / (ms * 1e-3) / 1e9
+    launches = max(1, info["launches"])
+    avg_launch_ms = ms / launches
+    alg_bytes_per_launch = updates * BYTES_PER_UPDATE / launches
+    achieved = alg_bytes_per_launch / (avg_launch_ms * 1e-3) / 1e9
+    del plan
+    torch.cuda.empty_cache()
+
+    # plain form on the first media of the same workload, and the batched form on the same subset
+    plain = None
+    if args.plain_media > 0 and args.mode == "batched":
+        k = min(args.plain_media, len(media))
+        sub, sub_dev, sub_obs = media[:k], mdev[:k], d_obs[:k]
+        pp = make_plan(sub, dtype, "plain", args, c_max)
+        pms, _ = time_gradient(pp, sub_dev, sub_obs, dtype, 1, 1, dev)
+        pu = pp.info["cell_updates"]
+        del pp
+        bp = make_plan(sub, dtype, "batched", args, c_max)
+        bms, _ = time_gradient(bp, sub_dev, sub_obs, dtype, 1, 1, dev)
+        del bp
+        torch.cuda.empty_cache()
+        plain = {"value": pu / (pms * 1e-3) / 1e9, "unit": "Gcell-updates/s", "media": k,
+                 "batched_same_media": pu / (bms * 1e-3) / 1e9,
+                 "speedup_batched_over_plain": pms / bms,
+                 "sample": f"first {k} medium(s) of the workload, {pu:.3e} cell-updates"}
+
+    cpu = None
+    if args.cpu_baseline:
+        cpu = run_cpu_baseline(media, args)
+
+    traffic = load_traffic()
+    line = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "Gcell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": dtype,
+        "data": "synthetic",
+        "config": {
+            "workload": desc,
+            "media": len(media),
+            "transmits": int(sum(m.geom.n_tx for m in media)),
+            "cell_updates_per_step": int(updates),
+            "recompute_updates_per_step": int(info["recompute_updates"]),
+            "mode": args.mode,
+            "group": info["group"], "rows": info["rows"], "waves": info["waves"],
+            "ckpt_min": info["min_ckpt"], "ckpt_max": info["max_ckpt"],
+            "launches_per_step": launches,
+            "workspace_gib": round(info["workspace_bytes"] / 2 ** 30, 2),
+            "parallelism": "single GPU",
+        },
+        "hbm_roofline_pct": round(100.0 * value * 1e9 * BYTES_PER_UPDATE / (HBM_PEAK_GBS * 1e9), 2),
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "step_kernel",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic,
+            "alg_bytes_per_launch": int(alg_bytes_per_launch),
+            "avg_launch_us": round(avg_launch_ms * 1e3, 3),
+        },
+        "plain": plain,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line))
+
+
+def run_cpu_baseline(media, args):
+    import numpy as np
+    import oracle
+    m = media[0]
+    g = m.geom
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or (os.cpu_count() or 1)
+    ntx = min(2, g.n_tx)
+    steps = args.cpu_steps
+    if steps <= 0:
+        # ~15 s at an assumed ~0.15 G updates/s per thread of the oracle, at most the full schedule
+        budget_updates = 15.0 * 0.15e9 * min(threads, 16)
+        steps = int(max(50, min(g.nt, budget_updates / (2 * g.nx * g.nz * ntx))))
+    import copy
+    gs = copy.copy(g)
+    gs.src = np.asarray(g.src)[:ntx]
+    gs.rcv = np.asarray(g.rcv)[:ntx]
+    gs.nt = steps
+    w = np.asarray(m.wavelet)[:ntx, :steps]
+    d_obs = np.zeros((ntx, steps, gs.n_rcv))
+    t0 = time.perf_counter()
+    oracle.run(gs, m.c, m.rho, w, d_obs=d_obs, threads=threads)
+    sec = time.perf_counter() - t0
+    upd = 2 * g.nx * g.nz * steps * ntx
+    return {"value": round(upd / sec / 1e9, 4), "unit": "Gcell-updates/s", "cores": threads, "kind": "oracle",
+            "seconds": round(sec, 2),
+            "sample": f"medium 0 ({g.nx}x{g.nz}), {ntx} transmits, first {steps} steps, FP64, d_obs = 0"}
+
+
+def load_traffic():
+    """HBM bytes per launch from the committed rocprofv3 counter runs, if they
+    were taken on the current kernel source (else null)."""
+    path = os.path.join(ROOT, "profiles", "step_kernel_traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    src = open(os.path.join(ROOT, "paper_2603_04070_amd", "csrc", "fwi_kernels.hpp"), "rb").read()
+    if rec.get("kernel_source_sha256") != hashlib.sha256(src).hexdigest():
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+if __name__ == "__main__":
+    main()

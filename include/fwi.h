@@ -119,6 +119,8 @@ typedef struct fwi_plan_info {
     int32_t launches;        /* step-kernel launches per gradient                               */
     int32_t max_ckpt;        /* largest K over items (nt when every plane is kept)              */
     int32_t min_ckpt;
+    int32_t waves;           /* groups of items run one after another to fit the memory budget */
+    int32_t reserved;
 } fwi_plan_info;
 
 /* Validate the geometry and options, copy the geometry, build the device

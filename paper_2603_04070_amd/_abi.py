@@ -56,6 +56,7 @@ class FwiPlanInfo(C.Structure):
         ("workspace_bytes", C.c_int64),
         ("n_items", C.c_int32), ("group", C.c_int32), ("rows", C.c_int32),
         ("launches", C.c_int32), ("max_ckpt", C.c_int32), ("min_ckpt", C.c_int32),
+        ("waves", C.c_int32), ("reserved", C.c_int32),
     ]
 
 

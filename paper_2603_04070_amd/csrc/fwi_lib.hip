@@ -36,6 +36,13 @@ struct ItemPlan {
     size_t src_off, tile_off_off, entry_off;    // plan-table byte offsets
 };
 
+struct Wave {
+    std::vector<int> items;    // items resident together in the state region
+    int blk0 = 0, nblk = 0;    // their blocks, contiguous in the block table
+    int steps = 0, fwd = 0, adj = 0;
+    size_t lam_off = 0, lam_bytes = 0;
+};
+
 struct MediumPlan {
     fwi_grid g;
     std::vector<int32_t> src, rcv;
@@ -57,14 +64,13 @@ struct fwi_plan {
     std::vector<MediumPlan> media;
     std::vector<ItemPlan> items;
     std::vector<int2> blocks;
-    int max_steps = 0, max_fwd = 0, max_adj = 0;
+    std::vector<Wave> waves;
     int64_t cell_updates = 0, recompute_updates = 0;
 
     // workspace layout
     size_t ws_bytes = 0;
     size_t zero_off = 0, zero_bytes = 0;
-    size_t clear_off = 0, clear_bytes = 0;       // accumulators + lambda planes (+ zero plane)
-    size_t lam_region_off = 0, lam_region_bytes = 0;
+    size_t clear_off = 0, clear_bytes = 0;       // zero plane + accumulators
     size_t acc_region_off = 0, acc_region_bytes = 0;
     size_t partial_off = 0;
 
@@ -283,7 +289,7 @@ static fwi_status create_impl(fwi_plan* p, fwi_dtype dtype, const fwi_grid* grid
         p->cell_updates += 2LL * m.g.nx * m.g.nz * m.g.nt * m.g.n_tx;
     }
 
-    // ---------------- checkpoint intervals under the memory budget
+    // ---------------- checkpoint intervals and waves under the memory budget
     double budget = o.mem_budget;
     if (budget <= 0) {
         size_t fr = 0, tot = 0;
@@ -313,44 +319,84 @@ static fwi_status create_impl(fwi_plan* p, fwi_dtype dtype, const fwi_grid* grid
         if (T == 1) K = 1;
         it.K = std::min(K, T);
     }
-    if (o.ckpt_interval == 0) {
-        // keep every plane for as many items as the budget allows
-        double used = 0;
-        for (auto& m : p->media) used += 2.0 * m.g.nx * m.g.nz * p->tsize + 2.0 * m.acc_slots * m.g.nx * m.g.nz * p->asize;
-        if (o.mode == FWI_PLAIN) {
+    size_t fixed = 0;
+    {
+        size_t zmax = 0;
+        for (auto& it : p->items) zmax = std::max(zmax, plane_bytes(it));
+        fixed += zmax + align_up((size_t)n_media * kMisfitBlocks * sizeof(double));
+        for (auto& m : p->media)
+            fixed += align_up((size_t)m.acc_slots * 2 * m.g.nx * m.g.nz * p->asize) +
+                     align_up((size_t)2 * m.g.nx * m.g.nz * p->tsize);
+    }
+    const double state_budget = budget - (double)fixed;
+    const int n_items = (int)p->items.size();
+    if (o.mode == FWI_PLAIN) {
+        // items run one after another and share one state slot
+        if (o.ckpt_interval == 0) {
             size_t mx_all = 0;
             for (auto& it : p->items) mx_all = std::max(mx_all, state_bytes(it, p->media[it.medium].g.nt));
-            if (used + mx_all <= budget)
+            if ((double)mx_all <= state_budget)
                 for (auto& it : p->items) it.K = p->media[it.medium].g.nt;
-        } else {
-            for (auto& it : p->items) used += state_bytes(it, it.K);
-            std::vector<int> order(p->items.size());
-            for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
-            std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-                return state_bytes(p->items[a], p->media[p->items[a].medium].g.nt) <
-                       state_bytes(p->items[b], p->media[p->items[b].medium].g.nt);
-            });
-            for (int i : order) {
-                ItemPlan& it = p->items[i];
-                const int T = p->media[it.medium].g.nt;
-                const double extra = (double)state_bytes(it, T) - (double)state_bytes(it, it.K);
-                if (used + extra <= budget) { used += extra; it.K = T; }
+        }
+        for (int i = 0; i < n_items; ++i) p->waves.push_back(Wave{{i}});
+    } else {
+        double total = 0;
+        for (auto& it : p->items) total += (double)state_bytes(it, it.K);
+        if (total <= state_budget) {
+            if (o.ckpt_interval == 0) {
+                // one wave: keep every plane for as many items as the budget allows
+                std::vector<int> order(n_items);
+                for (int i = 0; i < n_items; ++i) order[i] = i;
+                std::stable_sort(order.begin(), order.end(), [&](int a2, int b2) {
+                    return state_bytes(p->items[a2], p->media[p->items[a2].medium].g.nt) <
+                           state_bytes(p->items[b2], p->media[p->items[b2].medium].g.nt);
+                });
+                for (int i : order) {
+                    ItemPlan& it = p->items[i];
+                    const int T = p->media[it.medium].g.nt;
+                    const double extra = (double)state_bytes(it, T) - (double)state_bytes(it, it.K);
+                    if (total + extra <= state_budget) { total += extra; it.K = T; }
+                }
             }
+            Wave w;
+            for (int i = 0; i < n_items; ++i) w.items.push_back(i);
+            p->waves.push_back(w);
+        } else {
+            // waves of items with similar schedule length, each within the budget
+            std::vector<int> order(n_items);
+            for (int i = 0; i < n_items; ++i) order[i] = i;
+            auto steps_of = [&](int i) {
+                const ItemPlan& it = p->items[i];
+                const int T = p->media[it.medium].g.nt, J = (T + it.K - 1) / it.K;
+                return 2 * T + it.K * (J - 1);
+            };
+            std::stable_sort(order.begin(), order.end(), [&](int a2, int b2) { return steps_of(a2) > steps_of(b2); });
+            Wave w;
+            double used = 0;
+            for (int i : order) {
+                const double sb = (double)state_bytes(p->items[i], p->items[i].K);
+                if (!w.items.empty() && used + sb > state_budget) {
+                    p->waves.push_back(w);
+                    w = Wave{};
+                    used = 0;
+                }
+                w.items.push_back(i);
+                used += sb;
+            }
+            if (!w.items.empty()) p->waves.push_back(w);
         }
     }
     for (auto& it : p->items) {
         const int T = p->media[it.medium].g.nt;
         it.J = (T + it.K - 1) / it.K;
         it.steps = 2 * T + it.K * (it.J - 1);
-        p->max_steps = std::max(p->max_steps, it.steps);
-        p->max_fwd = std::max(p->max_fwd, T);
-        p->max_adj = std::max(p->max_adj, it.steps - T);
         const MediumPlan& m = p->media[it.medium];
         p->recompute_updates += (int64_t)it.K * (it.J - 1) * m.g.nx * m.g.nz * it.g_used;
     }
 
     // ---------------- workspace layout:
-    // [zero plane][accumulators][lambda planes][misfit partials][coefficients][checkpoints][segments]
+    // [zero plane][accumulators][misfit partials][coefficients][state of one wave]
+    // with a wave's state laid out as [lambda planes of its items][checkpoints][segments]
     size_t off = 0;
     size_t zmax = 0;
     for (auto& it : p->items) zmax = std::max(zmax, plane_bytes(it));
@@ -361,35 +407,31 @@ static fwi_status create_impl(fwi_plan* p, fwi_dtype dtype, const fwi_grid* grid
         off += align_up((size_t)m.acc_slots * 2 * m.g.nx * m.g.nz * p->asize);
     }
     p->acc_region_bytes = off - p->acc_region_off;
-    p->lam_region_off = off;
-    if (o.mode == FWI_PLAIN) {
-        size_t mx = 0;
-        for (auto& it : p->items) mx = std::max(mx, plane_bytes(it));
-        for (auto& it : p->items) it.lam_off = off;
-        off += 2 * mx;
-    } else {
-        for (auto& it : p->items) { it.lam_off = off; off += 2 * plane_bytes(it); }
-    }
-    p->lam_region_bytes = off - p->lam_region_off;
     p->clear_off = p->zero_off;
     p->clear_bytes = off - p->zero_off;
     p->partial_off = off;
     off += align_up((size_t)n_media * kMisfitBlocks * sizeof(double));
     for (auto& m : p->media) { m.coef_off = off; off += align_up((size_t)2 * m.g.nx * m.g.nz * p->tsize); }
-    if (o.mode == FWI_PLAIN) {
-        size_t mx_ck = 0, mx_seg = 0;
-        for (auto& it : p->items) {
-            mx_ck = std::max(mx_ck, plane_bytes(it) * 2 * (size_t)(it.J - 1));
-            mx_seg = std::max(mx_seg, plane_bytes(it) * (size_t)it.K);
+    const size_t state_off = off;
+    size_t state_max = 0;
+    for (auto& w : p->waves) {
+        size_t o2 = state_off;
+        w.lam_off = o2;
+        for (int i : w.items) { p->items[i].lam_off = o2; o2 += 2 * plane_bytes(p->items[i]); }
+        w.lam_bytes = o2 - w.lam_off;
+        for (int i : w.items) { p->items[i].ck_off = o2; o2 += plane_bytes(p->items[i]) * 2 * (size_t)(p->items[i].J - 1); }
+        for (int i : w.items) { p->items[i].seg_off = o2; o2 += plane_bytes(p->items[i]) * (size_t)p->items[i].K; }
+        state_max = std::max(state_max, o2 - state_off);
+        w.steps = w.fwd = w.adj = 0;
+        for (int i : w.items) {
+            const ItemPlan& it = p->items[i];
+            const int T = p->media[it.medium].g.nt;
+            w.steps = std::max(w.steps, it.steps);
+            w.fwd = std::max(w.fwd, T);
+            w.adj = std::max(w.adj, it.steps - T);
         }
-        for (auto& it : p->items) { it.ck_off = off; }
-        off += mx_ck;
-        for (auto& it : p->items) { it.seg_off = off; }
-        off += mx_seg;
-    } else {
-        for (auto& it : p->items) { it.ck_off = off; off += plane_bytes(it) * 2 * (size_t)(it.J - 1); }
-        for (auto& it : p->items) { it.seg_off = off; off += plane_bytes(it) * (size_t)it.K; }
     }
+    off += state_max;
     p->ws_bytes = off;
     for (auto& it : p->items) {
         const MediumPlan& m = p->media[it.medium];
@@ -453,10 +495,14 @@ static fwi_status create_impl(fwi_plan* p, fwi_dtype dtype, const fwi_grid* grid
         it.tile_off_off = tab_put(toff.data(), toff.size() * 4);
         it.entry_off = tab_put(ent.data(), ent.size() * sizeof(Entry));
     }
-    for (size_t i = 0; i < p->items.size(); ++i) {
-        ItemPlan& it = p->items[i];
-        it.blk0 = (int)p->blocks.size();
-        for (int t = 0; t < it.n_tiles; ++t) p->blocks.push_back(make_int2((int)i, t));
+    for (auto& w : p->waves) {
+        w.blk0 = (int)p->blocks.size();
+        for (int i : w.items) {
+            ItemPlan& it = p->items[i];
+            it.blk0 = (int)p->blocks.size();
+            for (int t = 0; t < it.n_tiles; ++t) p->blocks.push_back(make_int2(i, t));
+        }
+        w.nblk = (int)p->blocks.size() - w.blk0;
     }
     const size_t blocks_off = tab_put(p->blocks.data(), p->blocks.size() * sizeof(int2));
     p->item_bytes = (p->dtype == FWI_F64 ? sizeof(Item<double, double>)
@@ -526,13 +572,10 @@ extern "C" fwi_status fwi_plan_get_info(const fwi_plan* p, fwi_plan_info* info)
     info->n_items = (int32_t)p->items.size();
     info->group = p->G;
     info->rows = p->rows;
-    if (p->opt.mode == FWI_PLAIN) {
-        int64_t l = 0;
-        for (auto& it : p->items) l += it.steps;
-        info->launches = (int32_t)std::min<int64_t>(l, INT32_MAX);
-    } else {
-        info->launches = p->max_steps;
-    }
+    int64_t l = 0;
+    for (auto& w : p->waves) l += w.steps;
+    info->launches = (int32_t)std::min<int64_t>(l, INT32_MAX);
+    info->waves = (int32_t)p->waves.size();
     info->max_ckpt = 0;
     info->min_ckpt = INT32_MAX;
     for (auto& it : p->items) {
@@ -637,28 +680,19 @@ void medium_kernels(fwi_plan* p, hipStream_t st, int which, unsigned char* ws)
 void enqueue_sequence(fwi_plan* p, hipStream_t st, unsigned char* ws, int call, bool want_grad)
 {
     hipLaunchKernelGGL(zero_kernel<unsigned>, dim3(1), dim3(64), 0, st, p->d_status, (int64_t)1);
+    // an execute without gradient outputs is a forward solve (+ misfit)
+    if (call == kExecute && !want_grad) call = kForward;
     if (call != kAdjoint) {
         zero_bytes(st, ws + p->clear_off, p->clear_bytes);
         medium_kernels(p, st, 0, ws);
     } else {
         zero_bytes(st, ws + p->acc_region_off, p->acc_region_bytes);
-        zero_bytes(st, ws + p->lam_region_off, p->lam_region_bytes);
     }
-    // an execute without gradient outputs is a forward solve (+ misfit)
-    if (call == kExecute && !want_grad) call = kForward;
     const int mode = call == kExecute ? kRunAll : call == kForward ? kRunFwdOnly : kRunAdjOnly;
-    if (p->opt.mode == FWI_BATCHED) {
-        const int S = call == kExecute ? p->max_steps : call == kForward ? p->max_fwd : p->max_adj;
-        const dim3 grid((unsigned)p->blocks.size());
-        for (int s = 0; s < S; ++s) step(p, grid, st, p->d_blocks, s, mode);
-    } else {
-        for (size_t i = 0; i < p->items.size(); ++i) {
-            const ItemPlan& it = p->items[i];
-            const int T = p->media[it.medium].g.nt;
-            const int S = call == kExecute ? it.steps : call == kForward ? T : it.steps - T;
-            if (call != kForward && i > 0) zero_bytes(st, ws + it.lam_off, p->lam_region_bytes);
-            for (int s = 0; s < S; ++s) step(p, dim3(it.n_tiles), st, p->d_blocks + it.blk0, s, mode);
-        }
+    for (const Wave& w : p->waves) {
+        const int S = call == kExecute ? w.steps : call == kForward ? w.fwd : w.adj;
+        if (call != kForward) zero_bytes(st, ws + w.lam_off, w.lam_bytes);
+        for (int s = 0; s < S; ++s) step(p, dim3(w.nblk), st, p->d_blocks + w.blk0, s, mode);
     }
     if (call != kAdjoint) medium_kernels(p, st, 1, ws);
     if (call != kForward) medium_kernels(p, st, 2, ws);
@@ -686,8 +720,9 @@ fwi_status run_call(fwi_plan* p, const fwi_io* io, void* workspace, size_t bytes
         }
     }
     if (call == kAdjoint && p->fwd_ws != workspace) return fail(p, FWI_ERR_STATE, "no forward state in this workspace");
-    if (call != kExecute && p->opt.mode == FWI_PLAIN && p->items.size() > 1)
-        return fail(p, FWI_ERR_INVALID, "plain mode keeps one transmit's state: forward/adjoint need FWI_BATCHED");
+    if (call != kExecute && p->waves.size() > 1)
+        return fail(p, FWI_ERR_INVALID, "forward/adjoint need every item resident at once: use FWI_BATCHED "
+                                        "with a memory budget that holds all items");
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     unsigned char* ws = reinterpret_cast<unsigned char*>(workspace);
 

@@ -258,6 +258,15 @@ def c4_batch(seed: int = 40, n_media: int = 64, steps_scale: float = 1.0,
     return media
 
 
+def partner_medium(m: Medium, seed: int) -> Medium:
+    """A second rod + Gaussian medium on the same grid and geometry (its
+    traces serve as observed data for ``m``)."""
+    g = m.geom
+    rng = np.random.default_rng(seed)
+    c, rho = rod_gaussian_medium(rng, g.nx, g.nz, g.h, g.npml)
+    return Medium(g, c, rho, m.wavelet, name=m.name + f"_obs{seed}")
+
+
 def small_random_medium(seed: int, nx: int, nz: int, nt: int, n_tx: int = 2,
                         n_rcv: int = 5, npml: int = 3, h: float = 1e-3,
                         courant: float = 0.4, contrast: float = 0.1,
