@@ -41,6 +41,8 @@ def parse():
     ap.add_argument("--rows", type=int, default=0)
     ap.add_argument("--ckpt", type=int, default=0)
     ap.add_argument("--graph", type=int, default=0)
+    ap.add_argument("--spl", type=int, default=0, help="time steps fused per launch (0: library default)")
+    ap.add_argument("--mem-frac", type=float, default=0.85, help="workspace budget as a fraction of free HBM")
     ap.add_argument("--plain-media", type=int, default=1, help="media of the workload timed in plain form (0: skip)")
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--cpu-steps", type=int, default=0, help="oracle sample steps (0: sized for ~15 s)")
@@ -76,21 +78,27 @@ def to_dev(media, dtype, dev):
     return out
 
 
-def make_plan(media, dtype, mode, args, c_max):
+def make_plan(media, dtype, mode, args, c_max, forward_only=False):
+    import torch
     import paper_2603_04070_amd as F
     grids = [F.GridSpec.of(m.geom, c_max) for m in media]
+    torch.cuda.empty_cache()
+    free, _ = torch.cuda.mem_get_info()
     return F.Plan(grids, dtype=dtype, mode=mode, ckpt=args.ckpt, group=args.group if mode == "batched" else 0,
-                  rows=args.rows, use_graph=bool(args.graph) and mode == "batched")
+                  rows=args.rows, use_graph=bool(args.graph) and mode == "batched",
+                  steps_per_launch=args.spl if mode == "batched" else 1, forward_only=forward_only,
+                  mem_budget=args.mem_frac * free)
 
 
 def observed(partners, dtype, args, c_max, dev):
     """Observed traces: forward solve of the partner media (batched form)."""
     import torch
     import paper_2603_04070_amd as F
-    plan = make_plan(partners, dtype, "batched", args, c_max)
+    plan = make_plan(partners, dtype, "batched", args, c_max, forward_only=True)
     ios = to_dev(partners, dtype, dev)
     outs = F.forward(plan, ios)
-    del plan
+    del plan, ios
+    torch.cuda.empty_cache()
     return [o["traces"] for o in outs]
 
 
@@ -210,6 +218,7 @@ def main():
             "recompute_updates_per_step": int(info["recompute_updates"]),
             "mode": args.mode,
             "group": info["group"], "rows": info["rows"], "waves": info["waves"],
+            "steps_per_launch": info["steps_per_launch"],
             "ckpt_min": info["min_ckpt"], "ckpt_max": info["max_ckpt"],
             "launches_per_step": launches,
             "workspace_gib": round(info["workspace_bytes"] / 2 ** 30, 2),

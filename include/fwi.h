@@ -98,11 +98,15 @@ typedef struct fwi_options {
                              /*    budget, else K ~ sqrt(2 nt)); >= nt keeps every plane;        */
                              /*    other values are raised to at least 2                         */
     int32_t group;           /* transmits advanced together per work item: 0 = automatic, 1,2,4 */
-    int32_t rows;            /* rows per thread in a tile (tile = 64 x 4*rows): 0 = tuned       */
+    int32_t rows;            /* rows per thread in a tile (tile = 64 x 4*rows): 0 = default     */
     int32_t use_graph;       /* 1: record the batched launch sequence once in a hipGraph and     */
                              /*    replay it (FWI_BATCHED only)                                  */
     int32_t acc_double;      /* 1: imaging accumulators in double for FWI_F32 (default 0)       */
-    int32_t reserved[2];
+    int32_t steps_per_launch;/* time steps fused per launch: 0 = default (2 batched, 1 plain),    */
+                             /*    1 or 2; 2 falls back to 1 when a wrapping segment buffer has  */
+                             /*    K < 4; with 2, rows must be 1, 2 or 4 (FP64: 1 or 2)           */
+    int32_t forward_only;    /* 1: traces and misfit only; no replay state is kept and           */
+                             /*    gradient or adjoint calls return FWI_ERR_INVALID              */
     double mem_budget;       /* bytes the workspace may use; 0 = 60% of free device memory      */
     const char *tune_cache;  /* JSON cache path of the tile autotuner, or NULL                   */
 } fwi_options;
@@ -120,7 +124,7 @@ typedef struct fwi_plan_info {
     int32_t max_ckpt;        /* largest K over items (nt when every plane is kept)              */
     int32_t min_ckpt;
     int32_t waves;           /* groups of items run one after another to fit the memory budget */
-    int32_t reserved;
+    int32_t steps_per_launch;/* time steps fused per launch actually used                       */
 } fwi_plan_info;
 
 /* Validate the geometry and options, copy the geometry, build the device

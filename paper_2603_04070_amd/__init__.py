@@ -91,7 +91,8 @@ class Plan:
 
     def __init__(self, grids: Sequence[GridSpec], dtype: str = "f32", mode: str = "batched",
                  ckpt: int = 0, group: int = 0, rows: int = 0, use_graph: bool = False,
-                 acc_double: bool = False, mem_budget: float = 0.0):
+                 acc_double: bool = False, mem_budget: float = 0.0, steps_per_launch: int = 0,
+                 forward_only: bool = False):
         lib = _lib()
         self.grids = list(grids)
         self.dtype = dtype
@@ -112,6 +113,8 @@ class Plan:
         opt.rows = int(rows)
         opt.use_graph = int(bool(use_graph))
         opt.acc_double = int(bool(acc_double))
+        opt.steps_per_launch = int(steps_per_launch)
+        opt.forward_only = int(bool(forward_only))
         opt.mem_budget = float(mem_budget)
         self._h = C.c_void_p()
         dt = _abi.FWI_F64 if dtype == "f64" else _abi.FWI_F32

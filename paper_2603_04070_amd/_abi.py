@@ -44,7 +44,7 @@ class FwiOptions(C.Structure):
     _fields_ = [
         ("mode", C.c_int32), ("ckpt_interval", C.c_int32), ("group", C.c_int32),
         ("rows", C.c_int32), ("use_graph", C.c_int32), ("acc_double", C.c_int32),
-        ("reserved", C.c_int32 * 2),
+        ("steps_per_launch", C.c_int32), ("forward_only", C.c_int32),
         ("mem_budget", C.c_double),
         ("tune_cache", C.c_char_p),
     ]
@@ -56,7 +56,7 @@ class FwiPlanInfo(C.Structure):
         ("workspace_bytes", C.c_int64),
         ("n_items", C.c_int32), ("group", C.c_int32), ("rows", C.c_int32),
         ("launches", C.c_int32), ("max_ckpt", C.c_int32), ("min_ckpt", C.c_int32),
-        ("waves", C.c_int32), ("reserved", C.c_int32),
+        ("waves", C.c_int32), ("steps_per_launch", C.c_int32),
     ]
 
 

@@ -58,6 +58,7 @@ struct Item {
     int32_t nx, nz, nt, g_used;      // g_used <= G real transmits
     int32_t K, J, tiles_x, n_tiles;
     int32_t n_rcv, tx0, inject_adj, sample;   // inject_adj: 1 if d_adj drives the adjoint
+    int32_t S, nlam, pad0, pad1;     // steps fused per launch; lambda planes (lam^tau in tau mod nlam)
     int64_t plane;                   // elements per field plane = nx*nz*G
     int64_t wavelet_stride;
     const T* coef;                   // [nz*nx] x (Q, bt)
@@ -73,8 +74,10 @@ struct Item {
     T* traces;                       // medium's [n_tx][nt][n_rcv]
     const T* d_obs;
     const T* d_adj;
-    const int32_t* tile_off;         // [n_tiles + 1]
+    const int32_t* tile_off;         // [n_tiles + 1]: receivers inside each tile
     const Entry* entries;
+    const int32_t* tile_off_x;       // [n_tiles + 1]: receivers inside each tile grown by one cell
+    const Entry* entries_x;
 };
 
 template <typename T, int G>
@@ -105,38 +108,55 @@ __device__ __forceinline__ Vec<T, G> vzero()
 
 struct Step {
     int phase;
-    int n;      // FWD/RECOMP: step index (produces u^{n+1}); ADJ: time t
+    int n;      // FWD/RECOMP: first step index (produces u^{n+1}); ADJ: first time t
     int j;      // segment
+    int count;  // steps of this launch (1 or 2)
 };
 
-// Position of an item with (T, K, J) at its local step s.
-__device__ __forceinline__ Step decode(int T, int K, int J, int s)
+// Position of an item with (T, K, J) at launch s of its schedule, with up to
+// S steps of one phase fused per launch: forward steps in runs of S, then the
+// last segment's adjoint steps, then per earlier segment its recompute and
+// its adjoint steps, each run cut into launches of S steps (the last one of a
+// run may be shorter).
+__device__ __forceinline__ Step decode(int T, int K, int J, int s, int S)
 {
-    Step r{kIdle, 0, 0};
+    Step r{kIdle, 0, 0, 0};
     if (s < 0) return r;
-    if (s < T) {
-        r.phase = kFwd; r.n = s; r.j = s / K;
+    const int nf = (T + S - 1) / S;
+    if (s < nf) {
+        r.phase = kFwd; r.n = s * S; r.j = r.n / K; r.count = min(S, T - r.n);
         return r;
     }
-    s -= T;
+    s -= nf;
     const int last = T - (J - 1) * K;
-    if (s < last) {
-        r.phase = kAdj; r.n = T + 1 - s; r.j = J - 1;
+    const int nl = (last + S - 1) / S;
+    if (s < nl) {
+        r.phase = kAdj; r.n = T + 1 - s * S; r.j = J - 1; r.count = min(S, last - s * S);
         return r;
     }
-    s -= last;
-    if (s < 2 * K * (J - 1)) {
-        const int blk = s / (2 * K), rem = s - blk * 2 * K;
+    s -= nl;
+    const int nk = (K + S - 1) / S;
+    if (s < 2 * nk * (J - 1)) {
+        const int blk = s / (2 * nk), rem = s - blk * 2 * nk;
         r.j = J - 2 - blk;
-        if (rem < K) { r.phase = kRecomp; r.n = r.j * K + rem; }
-        else { r.phase = kAdj; r.n = r.j * K + K + 1 - (rem - K); }
+        if (rem < nk) {
+            r.phase = kRecomp; r.n = r.j * K + rem * S; r.count = min(S, K - rem * S);
+        } else {
+            const int m = rem - nk;
+            r.phase = kAdj; r.n = r.j * K + K + 1 - m * S; r.count = min(S, K - m * S);
+        }
     }
     return r;
 }
 
+// The per-cell arithmetic below spells out every fused multiply-add and
+// disables contraction, so that every kernel (one step per launch, either
+// half of a two-step launch, first pass or recompute) rounds a cell exactly
+// the same way: checkpointed replay then reproduces the first pass bitwise.
 template <typename T>
 __device__ __forceinline__ void damp_coeffs(T e, T& a, T& b)
 {
+#pragma clang fp contract(off)
     if (e == T(0)) {
         a = T(2);
         b = T(-1);
@@ -147,46 +167,171 @@ __device__ __forceinline__ void damp_coeffs(T e, T& a, T& b)
     }
 }
 
-// Forward-type step (FWD or RECOMP) on one tile.
-template <typename T, int G, typename Acc>
-__device__ void tile_forward(const Item<T, Acc>& it, const Step& st, int tile_x, int tile_z,
-                             int rows, bool sample)
+// One cell of the forward update: a u0 + b up + q sum_f b_f (u_f - u0).
+template <typename T>
+__device__ __forceinline__ T fwd_cell(T a, T b, T q, T fw, T fe, T fn, T fs, T u0, T uw, T ue, T un, T us, T up)
 {
-    const int nx = it.nx, nz = it.nz, K = it.K, n = st.n, j = st.j;
-    const int64_t P = it.plane;
-    // u^tau: zero for tau <= 0; on recompute the segment's first two planes come
-    // from checkpoint pair j; otherwise the segment buffer slot (tau - 1) mod K.
-    auto plane = [&](int tau) -> const T* {
-        if (tau <= 0) return it.zero;
-        if (st.phase == kRecomp && tau <= j * K)
-            return it.ck + (int64_t)(2 * (j - 1) + (tau == j * K ? 1 : 0)) * P;
-        return it.seg + (int64_t)((tau - 1) % K) * P;
-    };
-    const T* cur = plane(n);
-    const T* prev = plane(n - 1);
-    T* out = it.seg + (int64_t)(n % K) * P;
-    T* ck_out = nullptr;
-    if (st.phase == kFwd && j + 1 <= it.J - 1) {
-        const int t1 = n + 1, jn = j + 1;
-        if (t1 == jn * K - 1) ck_out = it.ck + (int64_t)(2 * (jn - 1)) * P;
-        else if (t1 == jn * K) ck_out = it.ck + (int64_t)(2 * (jn - 1) + 1) * P;
-    }
-    // source samples of this step
-    T wv[G];
-    int sc[G];
+#pragma clang fp contract(off)
+    T L = fw * (uw - u0);
+    L = fma(fe, ue - u0, L);
+    L = fma(fn, un - u0, L);
+    L = fma(fs, us - u0, L);
+    return fma(q, L, fma(b, up, a * u0));
+}
+
+// One cell of the adjoint update: a l0 + b lp + sum_f b_f (w_f - w0), w = q l.
+template <typename T>
+__device__ __forceinline__ T adj_cell(T a, T b, T fw, T fe, T fn, T fs, T w0, T ww, T we, T wn, T ws, T l0, T lp)
+{
+#pragma clang fp contract(off)
+    T L = fw * (ww - w0);
+    L = fma(fe, we - w0, L);
+    L = fma(fn, wn - w0, L);
+    L = fma(fs, ws - w0, L);
+    return fma(a, l0, fma(b, lp, L));
+}
+
+// Zero-lag imaging terms of one cell: S_kappa += l0 sum_f b_f du_f,
+// S_b += sum_f c_f du_f dw_f (c_f = 1/2 on interior faces, 1 on border faces).
+template <typename T>
+__device__ __forceinline__ void image_cell(T fw, T fe, T fn, T fs, T cw, T ce, T cn, T cs, T l0, T w0, T ww, T we,
+                                           T wn, T ws, T u0, T uw, T ue, T un, T us, T& sk, T& sb)
+{
+#pragma clang fp contract(off)
+    const T duw = uw - u0, due = ue - u0, dun = un - u0, dus = us - u0;
+    T Lu = fw * duw;
+    Lu = fma(fe, due, Lu);
+    Lu = fma(fn, dun, Lu);
+    Lu = fma(fs, dus, Lu);
+    T gb = (cw * duw) * (ww - w0);
+    gb = fma(ce * due, we - w0, gb);
+    gb = fma(cn * dun, wn - w0, gb);
+    gb = fma(cs * dus, ws - w0, gb);
+    sk = l0 * Lu;
+    sb = gb;
+}
+
+// Face buoyancies of a cell from its own and its neighbours' bt (border rule
+// bt_f = bt_x where the neighbour is outside the grid).
+template <typename T>
+__device__ __forceinline__ void faces(bool hw, bool he, bool hn, bool hs, T bc, T bw, T be, T bn, T bs,
+                                      T& fw, T& fe, T& fn, T& fs)
+{
+    const T hf = T(0.5);
+    fw = hw ? hf * (bc + bw) : bc;
+    fe = he ? hf * (bc + be) : bc;
+    fn = hn ? hf * (bc + bn) : bc;
+    fs = hs ? hf * (bc + bs) : bc;
+}
+
+// Plane of u^tau for a forward-type step: zero for tau <= 0; on recompute,
+// the checkpoint pair of segment j for tau <= jK; else segment slot (tau-1) mod K.
+template <typename T, typename Acc>
+__device__ __forceinline__ const T* fwd_plane(const Item<T, Acc>& it, const Step& st, int tau)
+{
+    if (tau <= 0) return it.zero;
+    if (st.phase == kRecomp && tau <= st.j * it.K)
+        return it.ck + (int64_t)(2 * (st.j - 1) + (tau == st.j * it.K ? 1 : 0)) * it.plane;
+    return it.seg + (int64_t)((tau - 1) % it.K) * it.plane;
+}
+
+// Checkpoint plane that u^{t1} is also written to during the first forward pass, or null.
+template <typename T, typename Acc>
+__device__ __forceinline__ T* ckpt_plane(const Item<T, Acc>& it, const Step& st, int t1)
+{
+    if (st.phase != kFwd) return nullptr;
+    const int jn = (t1 - 1) / it.K + 1;   // segment after the one holding u^{t1}
+    if (jn > it.J - 1) return nullptr;
+    if (t1 == jn * it.K - 1) return it.ck + (int64_t)(2 * (jn - 1)) * it.plane;
+    if (t1 == jn * it.K) return it.ck + (int64_t)(2 * (jn - 1) + 1) * it.plane;
+    return nullptr;
+}
+
+template <typename T, int G>
+struct Src {
+    int cell[G];
+    T w[G];
+};
+
+template <typename T, int G, typename Acc>
+__device__ __forceinline__ Src<T, G> sources(const Item<T, Acc>& it, int n)
+{
+    Src<T, G> s;
 #pragma unroll
     for (int g = 0; g < G; ++g) {
-        sc[g] = it.src[g];
-        wv[g] = sc[g] >= 0 ? it.wavelet[(int64_t)(it.tx0 + g) * it.wavelet_stride + n] : T(0);
+        s.cell[g] = it.src[g];
+        s.w[g] = s.cell[g] >= 0 ? it.wavelet[(int64_t)(it.tx0 + g) * it.wavelet_stride + n] : T(0);
     }
+    return s;
+}
+
+// Traces d[n] (and d[n+1] from out2) at the receivers of one tile, read back
+// after the whole workgroup has stored its cells.
+template <typename T, typename Acc>
+__device__ __forceinline__ void sample_tile(const Item<T, Acc>& it, int tile, int n, const T* out, const T* out2)
+{
+    const int e0 = it.tile_off[tile], e1 = it.tile_off[tile + 1];
+    if (e1 <= e0) return;
+    __syncthreads();
+    const int tid = threadIdx.y * kTileX + threadIdx.x;
+    for (int e = e0 + tid; e < e1; e += kBlock) {
+        const Entry en = it.entries[e];
+        it.traces[en.trace_off + (int64_t)n * it.n_rcv] = out[en.slot];
+        if (out2) it.traces[en.trace_off + (int64_t)(n + 1) * it.n_rcv] = out2[en.slot];
+    }
+}
+
+// Adjoint source of sample m (transmit, receiver) at one entry.
+template <typename T, typename Acc>
+__device__ __forceinline__ T adj_source(const Item<T, Acc>& it, const Entry& en, int m)
+{
+    const int64_t o = en.trace_off + (int64_t)m * it.n_rcv;
+    return it.inject_adj ? it.d_adj[o] : T(2) * (it.traces[o] - it.d_obs[o]);
+}
+
+template <typename T, typename Acc>
+__device__ __forceinline__ bool has_adj_source(const Item<T, Acc>& it)
+{
+    return it.inject_adj ? it.d_adj != nullptr : it.d_obs != nullptr;
+}
+
+// Add the adjoint source of sample m to field plane ``f`` at the receivers of
+// one tile (one thread per run of equal slots, entries of a run in order).
+template <typename T, typename Acc>
+__device__ __forceinline__ void inject_tile(const Item<T, Acc>& it, int tile, int m, T* f)
+{
+    const int e0 = it.tile_off[tile], e1 = it.tile_off[tile + 1];
+    if (e1 <= e0 || m < 0 || !has_adj_source(it)) return;
+    __syncthreads();
+    const int tid = threadIdx.y * kTileX + threadIdx.x;
+    for (int e = e0 + tid; e < e1; e += kBlock) {
+        const Entry en = it.entries[e];
+        if (en.run == 0) continue;
+        T s = T(0);
+        for (int k = 0; k < en.run; ++k) s += adj_source(it, it.entries[e + k], m);
+        f[en.slot] += s;
+    }
+}
+
+// ============================================================== one step per launch
+
+// Forward-type step (FWD or RECOMP) on one tile, straight from global memory:
+// each lane marches ``rows`` rows keeping the vertical neighbours in registers.
+template <typename T, int G, typename Acc>
+__device__ void tile_forward(const Item<T, Acc>& it, const Step& st, int tile_x, int tile_z, int rows, bool sample)
+{
+    const int nx = it.nx, nz = it.nz, n = st.n;
+    const T* cur = fwd_plane(it, st, n);
+    const T* prev = fwd_plane(it, st, n - 1);
+    T* out = it.seg + (int64_t)(n % it.K) * it.plane;
+    T* ck_out = ckpt_plane(it, st, n + 1);
+    const Src<T, G> src = sources<T, G>(it, n);
 
     const int ix = tile_x * kTileX + (int)threadIdx.x;
     const int z0 = tile_z * kWavesZ * rows + (int)threadIdx.y * rows;
-    const bool colok = ix < nx;
-    if (colok && z0 < nz) {
-        T ex = it.ex[ix];
+    if (ix < nx && z0 < nz) {
+        const T ex = it.ex[ix];
         const T* cf = it.coef;
-        // rolling values of the row above and the current row
         int iz = z0;
         int64_t x = (int64_t)iz * nx + ix;
         Vec<T, G> un = iz > 0 ? vload<T, G>(cur, x - nx) : vzero<T, G>();
@@ -195,32 +340,24 @@ __device__ void tile_forward(const Item<T, Acc>& it, const Step& st, int tile_x,
         T q = cf[2 * x], bc = cf[2 * x + 1];
         const int zend = min(z0 + rows, nz);
         for (; iz < zend; ++iz, x += nx) {
-            const bool has_s = iz < nz - 1;
-            Vec<T, G> us = has_s ? vload<T, G>(cur, x + nx) : vzero<T, G>();
-            T qs = has_s ? cf[2 * (x + nx)] : T(0);
-            T bs = has_s ? cf[2 * (x + nx) + 1] : T(0);
-            Vec<T, G> uw = ix > 0 ? vload<T, G>(cur, x - 1) : vzero<T, G>();
-            Vec<T, G> ue = ix < nx - 1 ? vload<T, G>(cur, x + 1) : vzero<T, G>();
-            const T bw = ix > 0 ? cf[2 * (x - 1) + 1] : T(0);
-            const T be = ix < nx - 1 ? cf[2 * (x + 1) + 1] : T(0);
-            const T hf = T(0.5);
-            const T fw = ix > 0 ? hf * (bc + bw) : bc;
-            const T fe = ix < nx - 1 ? hf * (bc + be) : bc;
-            const T fn = iz > 0 ? hf * (bc + bn) : bc;
-            const T fs = has_s ? hf * (bc + bs) : bc;
+            const bool hs = iz < nz - 1, hw = ix > 0, he = ix < nx - 1;
+            const Vec<T, G> us = hs ? vload<T, G>(cur, x + nx) : vzero<T, G>();
+            const T qs = hs ? cf[2 * (x + nx)] : T(0);
+            const T bs = hs ? cf[2 * (x + nx) + 1] : T(0);
+            const Vec<T, G> uw = hw ? vload<T, G>(cur, x - 1) : vzero<T, G>();
+            const Vec<T, G> ue = he ? vload<T, G>(cur, x + 1) : vzero<T, G>();
+            const T bw = hw ? cf[2 * (x - 1) + 1] : T(0);
+            const T be = he ? cf[2 * (x + 1) + 1] : T(0);
+            T fw, fe, fn, fs;
+            faces<T>(hw, he, iz > 0, hs, bc, bw, be, bn, bs, fw, fe, fn, fs);
             T a, b;
             damp_coeffs<T>(ex + it.ez[iz], a, b);
             const Vec<T, G> up = vload<T, G>(prev, x);
             Vec<T, G> r;
 #pragma unroll
             for (int g = 0; g < G; ++g) {
-                const T u0 = uc.v[g];
-                T L = fw * (uw.v[g] - u0);
-                L += fe * (ue.v[g] - u0);
-                L += fn * (un.v[g] - u0);
-                L += fs * (us.v[g] - u0);
-                T v = a * u0 + b * up.v[g] + q * L;
-                if ((int)x == sc[g]) v += wv[g];
+                T v = fwd_cell<T>(a, b, q, fw, fe, fn, fs, uc.v[g], uw.v[g], ue.v[g], un.v[g], us.v[g], up.v[g]);
+                if ((int)x == src.cell[g]) v += src.w[g];
                 r.v[g] = v;
             }
             vstore<T, G>(out, x, r);
@@ -229,30 +366,19 @@ __device__ void tile_forward(const Item<T, Acc>& it, const Step& st, int tile_x,
             bn = bc; bc = bs; q = qs;
         }
     }
-    if (sample) {
-        const int tile = tile_z * it.tiles_x + tile_x;
-        const int e0 = it.tile_off[tile], e1 = it.tile_off[tile + 1];
-        if (e1 > e0) {
-            __syncthreads();
-            const int tid = threadIdx.y * kTileX + threadIdx.x;
-            for (int e = e0 + tid; e < e1; e += kBlock) {
-                const Entry en = it.entries[e];
-                it.traces[en.trace_off + (int64_t)n * it.n_rcv] = out[en.slot];
-            }
-        }
-    }
+    if (sample) sample_tile(it, tile_z * it.tiles_x + tile_x, n, out, (const T*)nullptr);
 }
 
 // Adjoint step at time t on one tile, with the imaging of lam^t and u^{t-1}.
 template <typename T, int G, typename Acc>
 __device__ void tile_adjoint(const Item<T, Acc>& it, const Step& st, int tile_x, int tile_z, int rows)
 {
-    const int nx = it.nx, nz = it.nz, K = it.K, t = st.n;
-    const int64_t P = it.plane;
-    const int64_t ncell = (int64_t)nx * nz;
-    const T* cur = it.lam + (int64_t)(t & 1) * P;          // lam^t
-    T* io = it.lam + (int64_t)((t + 1) & 1) * P;           // lam^{t+1} in, lam^{t-1} out
-    const T* um = it.seg + (int64_t)((t - 2) % K) * P;     // u^{t-1}
+    const int nx = it.nx, nz = it.nz, t = st.n;
+    const int64_t P = it.plane, ncell = (int64_t)nx * nz;
+    const T* cur = it.lam + (int64_t)(t % it.nlam) * P;          // lam^t
+    const T* p1 = it.lam + (int64_t)((t + 1) % it.nlam) * P;     // lam^{t+1}
+    T* out = it.lam + (int64_t)((t - 1) % it.nlam) * P;          // lam^{t-1} (in place when nlam = 2)
+    const T* um = it.seg + (int64_t)((t - 2) % it.K) * P;        // u^{t-1}
     Acc* accK = it.acc;
     Acc* accB = it.acc + ncell;
 
@@ -261,11 +387,11 @@ __device__ void tile_adjoint(const Item<T, Acc>& it, const Step& st, int tile_x,
     if (ix < nx && z0 < nz) {
         const T ex = it.ex[ix];
         const T* cf = it.coef;
+        const bool hw = ix > 0, he = ix < nx - 1;
         const T hf = T(0.5);
-        const T cw = ix > 0 ? hf : T(1), ce = ix < nx - 1 ? hf : T(1);
+        const T cw = hw ? hf : T(1), ce = he ? hf : T(1);
         int iz = z0;
         int64_t x = (int64_t)iz * nx + ix;
-        // rolling (above, centre): lam, Q*lam, u, bt
         Vec<T, G> ln = iz > 0 ? vload<T, G>(cur, x - nx) : vzero<T, G>();
         Vec<T, G> lc = vload<T, G>(cur, x);
         Vec<T, G> uN = iz > 0 ? vload<T, G>(um, x - nx) : vzero<T, G>();
@@ -275,102 +401,437 @@ __device__ void tile_adjoint(const Item<T, Acc>& it, const Step& st, int tile_x,
         T qc = cf[2 * x], bc = cf[2 * x + 1];
         const int zend = min(z0 + rows, nz);
         for (; iz < zend; ++iz, x += nx) {
-            const bool has_s = iz < nz - 1;
-            const Vec<T, G> ls = has_s ? vload<T, G>(cur, x + nx) : vzero<T, G>();
-            const Vec<T, G> uS = has_s ? vload<T, G>(um, x + nx) : vzero<T, G>();
-            const T qs = has_s ? cf[2 * (x + nx)] : T(0);
-            const T bs = has_s ? cf[2 * (x + nx) + 1] : T(0);
-            const Vec<T, G> lw = ix > 0 ? vload<T, G>(cur, x - 1) : vzero<T, G>();
-            const Vec<T, G> le = ix < nx - 1 ? vload<T, G>(cur, x + 1) : vzero<T, G>();
-            const Vec<T, G> uW = ix > 0 ? vload<T, G>(um, x - 1) : vzero<T, G>();
-            const Vec<T, G> uE = ix < nx - 1 ? vload<T, G>(um, x + 1) : vzero<T, G>();
-            const T qw = ix > 0 ? cf[2 * (x - 1)] : T(0);
-            const T bw = ix > 0 ? cf[2 * (x - 1) + 1] : T(0);
-            const T qe = ix < nx - 1 ? cf[2 * (x + 1)] : T(0);
-            const T be = ix < nx - 1 ? cf[2 * (x + 1) + 1] : T(0);
-            const T fw = ix > 0 ? hf * (bc + bw) : bc;
-            const T fe = ix < nx - 1 ? hf * (bc + be) : bc;
-            const T fn = iz > 0 ? hf * (bc + bn) : bc;
-            const T fs = has_s ? hf * (bc + bs) : bc;
-            const T cn = iz > 0 ? hf : T(1), cs = has_s ? hf : T(1);
+            const bool hs = iz < nz - 1, hn = iz > 0;
+            const Vec<T, G> ls = hs ? vload<T, G>(cur, x + nx) : vzero<T, G>();
+            const Vec<T, G> uS = hs ? vload<T, G>(um, x + nx) : vzero<T, G>();
+            const T qs = hs ? cf[2 * (x + nx)] : T(0);
+            const T bs = hs ? cf[2 * (x + nx) + 1] : T(0);
+            const Vec<T, G> lw = hw ? vload<T, G>(cur, x - 1) : vzero<T, G>();
+            const Vec<T, G> le = he ? vload<T, G>(cur, x + 1) : vzero<T, G>();
+            const Vec<T, G> uW = hw ? vload<T, G>(um, x - 1) : vzero<T, G>();
+            const Vec<T, G> uE = he ? vload<T, G>(um, x + 1) : vzero<T, G>();
+            const T qw = hw ? cf[2 * (x - 1)] : T(0);
+            const T bw = hw ? cf[2 * (x - 1) + 1] : T(0);
+            const T qe = he ? cf[2 * (x + 1)] : T(0);
+            const T be = he ? cf[2 * (x + 1) + 1] : T(0);
+            T fw, fe, fn, fs;
+            faces<T>(hw, he, hn, hs, bc, bw, be, bn, bs, fw, fe, fn, fs);
+            const T cn = hn ? hf : T(1), cs = hs ? hf : T(1);
             T a, b;
             damp_coeffs<T>(ex + it.ez[iz], a, b);
-            const Vec<T, G> lp = vload<T, G>(io, x);
+            const Vec<T, G> lp = vload<T, G>(p1, x);
             Vec<T, G> r;
             Acc sk = Acc(0), sb = Acc(0);
 #pragma unroll
             for (int g = 0; g < G; ++g) {
-                const T l0 = lc.v[g];
-                const T w0 = qc * l0;
-                const T dww = qw * lw.v[g] - w0, dwe = qe * le.v[g] - w0;
-                const T dwn = qn * ln.v[g] - w0, dws = qs * ls.v[g] - w0;
-                T L = fw * dww;
-                L += fe * dwe;
-                L += fn * dwn;
-                L += fs * dws;
-                r.v[g] = a * l0 + b * lp.v[g] + L;
-                const T u0 = uC.v[g];
-                const T duw = uW.v[g] - u0, due = uE.v[g] - u0;
-                const T dun = uN.v[g] - u0, dus = uS.v[g] - u0;
-                T Lu = fw * duw;
-                Lu += fe * due;
-                Lu += fn * dun;
-                Lu += fs * dus;
-                T gb = cw * duw * dww;
-                gb += ce * due * dwe;
-                gb += cn * dun * dwn;
-                gb += cs * dus * dws;
-                sk += Acc(l0 * Lu);
-                sb += Acc(gb);
+                const T w0 = qc * lc.v[g], ww = qw * lw.v[g], we = qe * le.v[g];
+                const T wn = qn * ln.v[g], ws = qs * ls.v[g];
+                r.v[g] = adj_cell<T>(a, b, fw, fe, fn, fs, w0, ww, we, wn, ws, lc.v[g], lp.v[g]);
+                T k1, b1;
+                image_cell<T>(fw, fe, fn, fs, cw, ce, cn, cs, lc.v[g], w0, ww, we, wn, ws, uC.v[g], uW.v[g],
+                              uE.v[g], uN.v[g], uS.v[g], k1, b1);
+                sk += Acc(k1);
+                sb += Acc(b1);
             }
-            vstore<T, G>(io, x, r);
+            vstore<T, G>(out, x, r);
             accK[x] += sk;
             accB[x] += sb;
             ln = lc; lc = ls; uN = uC; uC = uS;
             qn = qc; qc = qs; bn = bc; bc = bs;
         }
     }
-    // adjoint source of lam^{t-1}: sample t-2 at the receivers of this tile
-    const int tile = tile_z * it.tiles_x + tile_x;
-    const int e0 = it.tile_off[tile], e1 = it.tile_off[tile + 1];
-    const bool has_src = it.inject_adj ? it.d_adj != nullptr : it.d_obs != nullptr;
-    if (e1 > e0 && t >= 2 && has_src) {
-        __syncthreads();
-        const int tid = threadIdx.y * kTileX + threadIdx.x;
-        const int64_t so = (int64_t)(t - 2) * it.n_rcv;
-        for (int e = e0 + tid; e < e1; e += kBlock) {
-            const Entry en = it.entries[e];
-            if (en.run == 0) continue;
-            T s = T(0);
-            for (int k = 0; k < en.run; ++k) {
-                const Entry ek = it.entries[e + k];
-                const int64_t o = ek.trace_off + so;
-                s += it.inject_adj ? it.d_adj[o] : T(2) * (it.traces[o] - it.d_obs[o]);
-            }
-            io[en.slot] += s;
-        }
-    }
+    // adjoint source of lam^{t-1}: sample t-2
+    inject_tile(it, tile_z * it.tiles_x + tile_x, t - 2, out);
 }
 
-// One step of every item whose schedule has work at this step.
-// blocks[b] = (item, tile); mode shifts/limits each item's local step.
+// ============================================================== two steps per launch
+//
+// The workgroup stages its tile grown by two cells (field and coefficients)
+// in LDS, computes the first step on the tile grown by one cell into LDS
+// and the second step on the tile itself; both time levels are stored (the
+// replay needs every plane).  The tile height is a compile-time constant so
+// that every global load of the launch is issued in one burst into
+// registers before the first barrier: a workgroup then waits for memory
+// once, not once per loop trip.
+
+template <typename T, int G, int R, bool ADJ>
+struct Lds2 {
+    static constexpr int TZ = kWavesZ * R;
+    static constexpr int W0 = kTileX + 4, H0 = TZ + 4, N0 = W0 * H0;   // tile grown by 2
+    static constexpr int W1 = kTileX + 2, H1 = TZ + 2, N1 = W1 * H1;   // tile grown by 1
+    static constexpr int P0 = (N0 + kBlock - 1) / kBlock;               // per-thread shares
+    static constexpr int P1 = (N1 + kBlock - 1) / kBlock;
+    // F0[N0] fields, C0[N0][2] coefficients, F1[N1] fields; adjoint also UA[N1], UB[N1]
+    static constexpr size_t bytes = ((size_t)N0 * (G + 2) + (size_t)N1 * G * (ADJ ? 3 : 1)) * sizeof(T);
+};
+
+template <typename T, int G, int R, bool ADJ>
+__device__ __forceinline__ void cell_of(int c, int grow, int x0, int z0, int& ix, int& iz)
+{
+    const int W = kTileX + 2 * grow;
+    ix = x0 - grow + c % W;
+    iz = z0 - grow + c / W;
+}
+
+template <typename T, int G, typename Acc, int R>
+__device__ void tile_forward2(const Item<T, Acc>& it, const Step& st, int tile_x, int tile_z, bool sample,
+                              unsigned char* smem)
+{
+    using L = Lds2<T, G, R, false>;
+    const int nx = it.nx, nz = it.nz, n = st.n;
+    Vec<T, G>* U0 = reinterpret_cast<Vec<T, G>*>(smem);                  // u^n
+    T* C0 = reinterpret_cast<T*>(U0 + L::N0);                            // (q, bt)
+    Vec<T, G>* U1 = reinterpret_cast<Vec<T, G>*>(C0 + 2 * L::N0);        // u^{n+1}
+    const T* cur = fwd_plane(it, st, n);
+    const T* prev = fwd_plane(it, st, n - 1);
+    T* out1 = it.seg + (int64_t)(n % it.K) * it.plane;
+    T* out2 = it.seg + (int64_t)((n + 1) % it.K) * it.plane;
+    T* ck1 = ckpt_plane(it, st, n + 1);
+    T* ck2 = ckpt_plane(it, st, n + 2);
+    const Src<T, G> s1 = sources<T, G>(it, n);
+    const Src<T, G> s2 = sources<T, G>(it, n + 1);
+    const int x0 = tile_x * kTileX, z0 = tile_z * L::TZ;
+    const int tid = threadIdx.y * kTileX + threadIdx.x;
+    const T* cf = it.coef;
+
+    // one burst: u^n and (q, bt) on the tile grown by 2, u^{n-1} on the tile grown by 1
+    Vec<T, G> f0[L::P0], pv[L::P1];
+    T q0[L::P0], b0[L::P0];
+#pragma unroll
+    for (int i = 0; i < L::P0; ++i) {
+        const int c = tid + i * kBlock;
+        int ix, iz;
+        cell_of<T, G, R, false>(c, 2, x0, z0, ix, iz);
+        const bool in = c < L::N0 && ix >= 0 && ix < nx && iz >= 0 && iz < nz;
+        const int64_t x = (int64_t)iz * nx + ix;
+        f0[i] = in ? vload<T, G>(cur, x) : vzero<T, G>();
+        q0[i] = in ? cf[2 * x] : T(0);
+        b0[i] = in ? cf[2 * x + 1] : T(0);
+    }
+#pragma unroll
+    for (int i = 0; i < L::P1; ++i) {
+        const int c = tid + i * kBlock;
+        int ix, iz;
+        cell_of<T, G, R, false>(c, 1, x0, z0, ix, iz);
+        const bool in = c < L::N1 && ix >= 0 && ix < nx && iz >= 0 && iz < nz;
+        pv[i] = in ? vload<T, G>(prev, (int64_t)iz * nx + ix) : vzero<T, G>();
+    }
+#pragma unroll
+    for (int i = 0; i < L::P0; ++i) {
+        const int c = tid + i * kBlock;
+        if (c < L::N0) {
+            U0[c] = f0[i];
+            C0[2 * c] = q0[i];
+            C0[2 * c + 1] = b0[i];
+        }
+    }
+    __syncthreads();
+    // step n on the tile grown by one cell
+#pragma unroll
+    for (int i = 0; i < L::P1; ++i) {
+        const int c = tid + i * kBlock;
+        if (c < L::N1) {
+            const int ex = c % L::W1, ez = c / L::W1;
+            const int ix = x0 - 1 + ex, iz = z0 - 1 + ez;
+            Vec<T, G> r = vzero<T, G>();
+            if (ix >= 0 && ix < nx && iz >= 0 && iz < nz) {
+                const int k = (ez + 1) * L::W0 + ex + 1;
+                const int64_t x = (int64_t)iz * nx + ix;
+                T fw, fe, fn, fs, a, b;
+                faces<T>(ix > 0, ix < nx - 1, iz > 0, iz < nz - 1, C0[2 * k + 1], C0[2 * (k - 1) + 1],
+                         C0[2 * (k + 1) + 1], C0[2 * (k - L::W0) + 1], C0[2 * (k + L::W0) + 1], fw, fe, fn, fs);
+                damp_coeffs<T>(it.ex[ix] + it.ez[iz], a, b);
+                const T q = C0[2 * k];
+                const Vec<T, G> u0 = U0[k], uw = U0[k - 1], ue = U0[k + 1], un = U0[k - L::W0], us = U0[k + L::W0];
+#pragma unroll
+                for (int g = 0; g < G; ++g) {
+                    T v = fwd_cell<T>(a, b, q, fw, fe, fn, fs, u0.v[g], uw.v[g], ue.v[g], un.v[g], us.v[g], pv[i].v[g]);
+                    if ((int)x == s1.cell[g]) v += s1.w[g];
+                    r.v[g] = v;
+                }
+                if (ex >= 1 && ex <= kTileX && ez >= 1 && ez <= L::TZ) {
+                    vstore<T, G>(out1, x, r);
+                    if (ck1) vstore<T, G>(ck1, x, r);
+                }
+            }
+            U1[c] = r;
+        }
+    }
+    __syncthreads();
+    // step n+1 on the tile
+    const int ix = x0 + (int)threadIdx.x;
+    if (ix < nx) {
+        const T exd = it.ex[ix];
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            const int ez = (int)threadIdx.y * R + k, iz = z0 + ez;
+            if (iz < nz) {
+                const int k1 = (ez + 1) * L::W1 + threadIdx.x + 1;
+                const int k0 = (ez + 2) * L::W0 + threadIdx.x + 2;
+                const int64_t x = (int64_t)iz * nx + ix;
+                T fw, fe, fn, fs, a, b;
+                faces<T>(ix > 0, ix < nx - 1, iz > 0, iz < nz - 1, C0[2 * k0 + 1], C0[2 * (k0 - 1) + 1],
+                         C0[2 * (k0 + 1) + 1], C0[2 * (k0 - L::W0) + 1], C0[2 * (k0 + L::W0) + 1], fw, fe, fn, fs);
+                damp_coeffs<T>(exd + it.ez[iz], a, b);
+                const T q = C0[2 * k0];
+                const Vec<T, G> u0 = U1[k1], uw = U1[k1 - 1], ue = U1[k1 + 1], un = U1[k1 - L::W1],
+                                us = U1[k1 + L::W1];
+                const Vec<T, G> up = U0[k0];
+                Vec<T, G> r;
+#pragma unroll
+                for (int g = 0; g < G; ++g) {
+                    T v = fwd_cell<T>(a, b, q, fw, fe, fn, fs, u0.v[g], uw.v[g], ue.v[g], un.v[g], us.v[g], up.v[g]);
+                    if ((int)x == s2.cell[g]) v += s2.w[g];
+                    r.v[g] = v;
+                }
+                vstore<T, G>(out2, x, r);
+                if (ck2) vstore<T, G>(ck2, x, r);
+            }
+        }
+    }
+    if (sample) sample_tile(it, tile_z * it.tiles_x + tile_x, n, out1, out2);
+}
+
+template <typename T, int G, typename Acc, int R>
+__device__ void tile_adjoint2(const Item<T, Acc>& it, const Step& st, int tile_x, int tile_z, unsigned char* smem)
+{
+    using L = Lds2<T, G, R, true>;
+    const int nx = it.nx, nz = it.nz, t = st.n, nl = it.nlam;
+    const int64_t P = it.plane, ncell = (int64_t)nx * nz;
+    Vec<T, G>* L0 = reinterpret_cast<Vec<T, G>*>(smem);                  // lam^t, tile + 2
+    T* C0 = reinterpret_cast<T*>(L0 + L::N0);                            // (q, bt), tile + 2
+    Vec<T, G>* L1 = reinterpret_cast<Vec<T, G>*>(C0 + 2 * L::N0);        // lam^{t-1}, tile + 1
+    Vec<T, G>* UA = L1 + L::N1;                                          // u^{t-1}, tile + 1
+    Vec<T, G>* UB = UA + L::N1;                                          // u^{t-2}, tile + 1
+    const T* cur = it.lam + (int64_t)(t % nl) * P;
+    const T* p1 = it.lam + (int64_t)((t + 1) % nl) * P;
+    T* out1 = it.lam + (int64_t)((t - 1) % nl) * P;
+    T* out2 = it.lam + (int64_t)((t - 2) % nl) * P;
+    const T* um1 = it.seg + (int64_t)((t - 2) % it.K) * P;
+    const T* um2 = it.seg + (int64_t)((t - 3) % it.K) * P;
+    const int x0 = tile_x * kTileX, z0 = tile_z * L::TZ;
+    const int tid = threadIdx.y * kTileX + threadIdx.x;
+    const int tile = tile_z * it.tiles_x + tile_x;
+    const T* cf = it.coef;
+
+    // one burst: lam^t and (q, bt) on the tile grown by 2; lam^{t+1}, u^{t-1},
+    // u^{t-2} on the tile grown by 1
+    Vec<T, G> f0[L::P0], pv[L::P1], ua[L::P1], ub[L::P1];
+    T q0[L::P0], b0[L::P0];
+#pragma unroll
+    for (int i = 0; i < L::P0; ++i) {
+        const int c = tid + i * kBlock;
+        int ix, iz;
+        cell_of<T, G, R, true>(c, 2, x0, z0, ix, iz);
+        const bool in = c < L::N0 && ix >= 0 && ix < nx && iz >= 0 && iz < nz;
+        const int64_t x = (int64_t)iz * nx + ix;
+        f0[i] = in ? vload<T, G>(cur, x) : vzero<T, G>();
+        q0[i] = in ? cf[2 * x] : T(0);
+        b0[i] = in ? cf[2 * x + 1] : T(0);
+    }
+#pragma unroll
+    for (int i = 0; i < L::P1; ++i) {
+        const int c = tid + i * kBlock;
+        int ix, iz;
+        cell_of<T, G, R, true>(c, 1, x0, z0, ix, iz);
+        const bool in = c < L::N1 && ix >= 0 && ix < nx && iz >= 0 && iz < nz;
+        const int64_t x = (int64_t)iz * nx + ix;
+        pv[i] = in ? vload<T, G>(p1, x) : vzero<T, G>();
+        ua[i] = in ? vload<T, G>(um1, x) : vzero<T, G>();
+        ub[i] = in ? vload<T, G>(um2, x) : vzero<T, G>();
+    }
+#pragma unroll
+    for (int i = 0; i < L::P0; ++i) {
+        const int c = tid + i * kBlock;
+        if (c < L::N0) {
+            L0[c] = f0[i];
+            C0[2 * c] = q0[i];
+            C0[2 * c + 1] = b0[i];
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < L::P1; ++i) {
+        const int c = tid + i * kBlock;
+        if (c < L::N1) {
+            UA[c] = ua[i];
+            UB[c] = ub[i];
+        }
+    }
+    __syncthreads();
+    // lam^{t-1} on the tile grown by one cell
+#pragma unroll
+    for (int i = 0; i < L::P1; ++i) {
+        const int c = tid + i * kBlock;
+        if (c < L::N1) {
+            const int ex = c % L::W1, ez = c / L::W1;
+            const int ix = x0 - 1 + ex, iz = z0 - 1 + ez;
+            Vec<T, G> r = vzero<T, G>();
+            if (ix >= 0 && ix < nx && iz >= 0 && iz < nz) {
+                const int k = (ez + 1) * L::W0 + ex + 1;
+                T fw, fe, fn, fs, a, b;
+                faces<T>(ix > 0, ix < nx - 1, iz > 0, iz < nz - 1, C0[2 * k + 1], C0[2 * (k - 1) + 1],
+                         C0[2 * (k + 1) + 1], C0[2 * (k - L::W0) + 1], C0[2 * (k + L::W0) + 1], fw, fe, fn, fs);
+                damp_coeffs<T>(it.ex[ix] + it.ez[iz], a, b);
+                const T qc = C0[2 * k], qw = C0[2 * (k - 1)], qe = C0[2 * (k + 1)], qn = C0[2 * (k - L::W0)],
+                        qs = C0[2 * (k + L::W0)];
+                const Vec<T, G> l0 = L0[k], lw = L0[k - 1], le = L0[k + 1], ln = L0[k - L::W0], ls = L0[k + L::W0];
+#pragma unroll
+                for (int g = 0; g < G; ++g)
+                    r.v[g] = adj_cell<T>(a, b, fw, fe, fn, fs, qc * l0.v[g], qw * lw.v[g], qe * le.v[g],
+                                         qn * ln.v[g], qs * ls.v[g], l0.v[g], pv[i].v[g]);
+            }
+            L1[c] = r;
+        }
+    }
+    // adjoint source of lam^{t-1} (sample t-2) at the receivers of the grown tile
+    {
+        const int e0 = it.tile_off_x[tile], e1 = it.tile_off_x[tile + 1];
+        __syncthreads();
+        if (e1 > e0 && has_adj_source(it)) {
+            for (int e = e0 + tid; e < e1; e += kBlock) {
+                const Entry en = it.entries_x[e];
+                if (en.run == 0) continue;
+                T sum = T(0);
+                for (int k = 0; k < en.run; ++k) sum += adj_source(it, it.entries_x[e + k], t - 2);
+                const int cell = en.slot / G, g = en.slot - cell * G;
+                const int ex = cell % nx - (x0 - 1), ez = cell / nx - (z0 - 1);
+                L1[ez * L::W1 + ex].v[g] += sum;
+            }
+            __syncthreads();
+        }
+    }
+    // on the tile: imaging of (lam^t, u^{t-1}), lam^{t-2}, imaging of (lam^{t-1}, u^{t-2})
+    const int ix = x0 + (int)threadIdx.x;
+    if (ix < nx) {
+        const T exd = it.ex[ix];
+        const bool hw = ix > 0, he = ix < nx - 1;
+        const T hf = T(0.5);
+        const T cw = hw ? hf : T(1), ce = he ? hf : T(1);
+        Acc* accK = it.acc;
+        Acc* accB = it.acc + ncell;
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            const int ez = (int)threadIdx.y * R + k, iz = z0 + ez;
+            if (iz < nz) {
+                const int k1 = (ez + 1) * L::W1 + threadIdx.x + 1;
+                const int k0 = (ez + 2) * L::W0 + threadIdx.x + 2;
+                const int64_t x = (int64_t)iz * nx + ix;
+                const bool hn = iz > 0, hs = iz < nz - 1;
+                T fw, fe, fn, fs, a, b;
+                faces<T>(hw, he, hn, hs, C0[2 * k0 + 1], C0[2 * (k0 - 1) + 1], C0[2 * (k0 + 1) + 1],
+                         C0[2 * (k0 - L::W0) + 1], C0[2 * (k0 + L::W0) + 1], fw, fe, fn, fs);
+                const T cn = hn ? hf : T(1), cs = hs ? hf : T(1);
+                damp_coeffs<T>(exd + it.ez[iz], a, b);
+                const T qc = C0[2 * k0], qw = C0[2 * (k0 - 1)], qe = C0[2 * (k0 + 1)], qn = C0[2 * (k0 - L::W0)],
+                        qs = C0[2 * (k0 + L::W0)];
+                const Vec<T, G> l0 = L0[k0], lw = L0[k0 - 1], le = L0[k0 + 1], ln = L0[k0 - L::W0],
+                                ls = L0[k0 + L::W0];
+                const Vec<T, G> m0 = L1[k1], mw = L1[k1 - 1], me = L1[k1 + 1], mn = L1[k1 - L::W1],
+                                ms = L1[k1 + L::W1];
+                const Vec<T, G> a0 = UA[k1], aw = UA[k1 - 1], ae = UA[k1 + 1], an = UA[k1 - L::W1],
+                                as = UA[k1 + L::W1];
+                const Vec<T, G> c0 = UB[k1], cw2 = UB[k1 - 1], ce2 = UB[k1 + 1], cn2 = UB[k1 - L::W1],
+                                cs2 = UB[k1 + L::W1];
+                Vec<T, G> r;
+                // the two time levels' imaging sums are added to the accumulators one
+                // after the other, exactly as two one-step launches would
+                Acc ska = Acc(0), sba = Acc(0), skb = Acc(0), sbb = Acc(0);
+#pragma unroll
+                for (int g = 0; g < G; ++g) {
+                    const T w0 = qc * l0.v[g], ww = qw * lw.v[g], we = qe * le.v[g], wn = qn * ln.v[g],
+                            ws = qs * ls.v[g];
+                    const T v0 = qc * m0.v[g], vw = qw * mw.v[g], ve = qe * me.v[g], vn = qn * mn.v[g],
+                            vs = qs * ms.v[g];
+                    r.v[g] = adj_cell<T>(a, b, fw, fe, fn, fs, v0, vw, ve, vn, vs, m0.v[g], l0.v[g]);
+                    T k1a, b1a, k1b, b1b;
+                    image_cell<T>(fw, fe, fn, fs, cw, ce, cn, cs, l0.v[g], w0, ww, we, wn, ws, a0.v[g], aw.v[g],
+                                  ae.v[g], an.v[g], as.v[g], k1a, b1a);
+                    image_cell<T>(fw, fe, fn, fs, cw, ce, cn, cs, m0.v[g], v0, vw, ve, vn, vs, c0.v[g], cw2.v[g],
+                                  ce2.v[g], cn2.v[g], cs2.v[g], k1b, b1b);
+                    ska += Acc(k1a);
+                    sba += Acc(b1a);
+                    skb += Acc(k1b);
+                    sbb += Acc(b1b);
+                }
+                vstore<T, G>(out1, x, m0);
+                vstore<T, G>(out2, x, r);
+                Acc vk = accK[x], vb = accB[x];
+                vk += ska;
+                vb += sba;
+                vk += skb;
+                vb += sbb;
+                accK[x] = vk;
+                accB[x] = vb;
+            }
+        }
+    }
+    // adjoint source of lam^{t-2}: sample t-3
+    inject_tile(it, tile, t - 3, out2);
+}
+
+// Item position at launch s of a call (mode shifts / limits the schedule).
+template <typename T, typename Acc>
+__device__ __forceinline__ Step item_step(const Item<T, Acc>& it, int s, int mode)
+{
+    int sl = s;
+    if (mode == kRunAdjOnly) sl = s + (it.nt + it.S - 1) / it.S;
+    Step st = decode(it.nt, it.K, it.J, sl, it.S);
+    if (mode == kRunFwdOnly && st.phase != kFwd) st.phase = kIdle;
+    return st;
+}
+
+// Forward-type launches of one step at launch s; blocks[b] = (item, tile).
 template <typename T, int G, typename Acc>
-__global__ __launch_bounds__(kBlock) void step_kernel(const Item<T, Acc>* __restrict__ items,
-                                                       const int2* __restrict__ blocks, int s,
-                                                       int mode, int rows)
+__global__ __launch_bounds__(kBlock) void fwd1_kernel(const Item<T, Acc>* __restrict__ items,
+                                                       const int2* __restrict__ blocks, int s, int mode, int rows)
 {
     const int2 bt = blocks[blockIdx.x];
+    if (bt.x < 0) return;
     const Item<T, Acc>& it = items[bt.x];
-    int sl = s;
-    if (mode == kRunAdjOnly) sl = s + it.nt;
-    Step st = decode(it.nt, it.K, it.J, sl);
-    if (mode == kRunFwdOnly && st.phase != kFwd) st.phase = kIdle;
-    if (st.phase == kIdle) return;
-    const int tile_x = bt.y % it.tiles_x, tile_z = bt.y / it.tiles_x;
-    if (st.phase == kAdj)
-        tile_adjoint<T, G, Acc>(it, st, tile_x, tile_z, rows);
-    else
-        tile_forward<T, G, Acc>(it, st, tile_x, tile_z, rows, st.phase == kFwd && it.sample);
+    const Step st = item_step(it, s, mode);
+    if ((st.phase != kFwd && st.phase != kRecomp) || st.count != 1) return;
+    tile_forward<T, G, Acc>(it, st, bt.y % it.tiles_x, bt.y / it.tiles_x, rows, st.phase == kFwd && it.sample);
+}
+
+// Forward-type launches of two steps, tiles of 64 x 4R cells.
+template <typename T, int G, typename Acc, int R>
+__global__ __launch_bounds__(kBlock) void fwd2_kernel(const Item<T, Acc>* __restrict__ items,
+                                                       const int2* __restrict__ blocks, int s, int mode)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int2 bt = blocks[blockIdx.x];
+    if (bt.x < 0) return;
+    const Item<T, Acc>& it = items[bt.x];
+    const Step st = item_step(it, s, mode);
+    if ((st.phase != kFwd && st.phase != kRecomp) || st.count != 2) return;
+    tile_forward2<T, G, Acc, R>(it, st, bt.y % it.tiles_x, bt.y / it.tiles_x, st.phase == kFwd && it.sample, smem);
+}
+
+// Adjoint + imaging launches of one step.
+template <typename T, int G, typename Acc>
+__global__ __launch_bounds__(kBlock) void adj1_kernel(const Item<T, Acc>* __restrict__ items,
+                                                       const int2* __restrict__ blocks, int s, int mode, int rows)
+{
+    const int2 bt = blocks[blockIdx.x];
+    if (bt.x < 0) return;
+    const Item<T, Acc>& it = items[bt.x];
+    const Step st = item_step(it, s, mode);
+    if (st.phase != kAdj || st.count != 1) return;
+    tile_adjoint<T, G, Acc>(it, st, bt.y % it.tiles_x, bt.y / it.tiles_x, rows);
+}
+
+// Adjoint + imaging launches of two steps, tiles of 64 x 4R cells.
+template <typename T, int G, typename Acc, int R>
+__global__ __launch_bounds__(kBlock) void adj2_kernel(const Item<T, Acc>* __restrict__ items,
+                                                       const int2* __restrict__ blocks, int s, int mode)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int2 bt = blocks[blockIdx.x];
+    if (bt.x < 0) return;
+    const Item<T, Acc>& it = items[bt.x];
+    const Step st = item_step(it, s, mode);
+    if (st.phase != kAdj || st.count != 2) return;
+    tile_adjoint2<T, G, Acc, R>(it, st, bt.y % it.tiles_x, bt.y / it.tiles_x, smem);
 }
 
 // ---------------------------------------------------------------- medium prep

@@ -23,6 +23,8 @@ namespace {
 thread_local std::string g_create_error;
 
 constexpr size_t kAlign = 256;
+constexpr int kXcd = 8;        // MI355X: 8 accelerator complex dies, each with its own L2
+constexpr size_t kLdsBytes = 160 * 1024;   // LDS per compute unit on gfx950
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct ItemPlan {
@@ -34,11 +36,13 @@ struct ItemPlan {
     int steps;                 // schedule length 2T + K(J-1)
     size_t seg_off, ck_off, lam_off, acc_off;   // workspace byte offsets
     size_t src_off, tile_off_off, entry_off;    // plan-table byte offsets
+    size_t tile_off_x_off, entry_x_off;         // receivers of each tile grown by one cell
 };
 
 struct Wave {
-    std::vector<int> items;    // items resident together in the state region
+    std::vector<int> items;    // items resident together, longest schedule first
     int blk0 = 0, nblk = 0;    // their blocks, contiguous in the block table
+    std::vector<int> prefix;   // prefix[m]: blocks covering the first m items
     int steps = 0, fwd = 0, adj = 0;
     size_t lam_off = 0, lam_bytes = 0;
 };
@@ -58,7 +62,7 @@ struct MediumPlan {
 struct fwi_plan {
     fwi_dtype dtype = FWI_F32;
     fwi_options opt{};
-    int G = 1, rows = 4;
+    int G = 1, rows = 4, S = 1, nlam = 2;
     bool acc_double = false;
     size_t tsize = 4, asize = 4;
     std::vector<MediumPlan> media;
@@ -164,30 +168,129 @@ fwi_status validate_grid(const fwi_grid& g, int idx, std::string& msg)
     return FWI_OK;
 }
 
-// Kernel table per (dtype, accumulator, G).
-template <typename T, typename Acc, int G>
-void launch_step(dim3 grid, hipStream_t st, const void* items, const int2* blocks, int s, int mode, int rows)
+// Step launches per (dtype, accumulator, G).  kind: 0 forward one step,
+// 1 forward two steps, 2 adjoint one step, 3 adjoint two steps.  Two-step
+// kernels exist for tile heights of 4, 8 and 16 rows (R = 1, 2, 4).
+template <typename T, typename Acc, int G, int R>
+void launch2(int kind, dim3 grid, hipStream_t st, const Item<T, Acc>* it, const int2* blocks, int s, int mode)
 {
-    hipLaunchKernelGGL((step_kernel<T, G, Acc>), grid, dim3(kTileX, kWavesZ), 0, st,
-                       reinterpret_cast<const Item<T, Acc>*>(items), blocks, s, mode, rows);
+    const dim3 blk(kTileX, kWavesZ);
+    constexpr size_t lds_f = Lds2<T, G, R, false>::bytes;
+    constexpr size_t lds_a = Lds2<T, G, R, true>::bytes;
+    if (kind == 1)
+        hipLaunchKernelGGL((fwd2_kernel<T, G, Acc, R>), grid, blk, lds_f, st, it, blocks, s, mode);
+    else
+        hipLaunchKernelGGL((adj2_kernel<T, G, Acc, R>), grid, blk, lds_a, st, it, blocks, s, mode);
+}
+
+template <typename T, typename Acc, int G>
+void launch_step(int kind, dim3 grid, hipStream_t st, const void* items, const int2* blocks, int s, int mode,
+                 int rows)
+{
+    const auto* it = reinterpret_cast<const Item<T, Acc>*>(items);
+    const dim3 blk(kTileX, kWavesZ);
+    if (kind == 0) {
+        hipLaunchKernelGGL((fwd1_kernel<T, G, Acc>), grid, blk, 0, st, it, blocks, s, mode, rows);
+    } else if (kind == 2) {
+        hipLaunchKernelGGL((adj1_kernel<T, G, Acc>), grid, blk, 0, st, it, blocks, s, mode, rows);
+    } else if (rows == 1) {
+        launch2<T, Acc, G, 1>(kind, grid, st, it, blocks, s, mode);
+    } else if (rows == 2) {
+        launch2<T, Acc, G, 2>(kind, grid, st, it, blocks, s, mode);
+    } else {
+        launch2<T, Acc, G, 4>(kind, grid, st, it, blocks, s, mode);
+    }
+}
+
+// Allow the two-step kernels more than the default 64 KiB of dynamic LDS.
+template <typename T, typename Acc, int G, int R>
+hipError_t allow_lds()
+{
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&fwd2_kernel<T, G, Acc, R>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)Lds2<T, G, R, false>::bytes);
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(&adj2_kernel<T, G, Acc, R>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)Lds2<T, G, R, true>::bytes);
+}
+
+template <typename T, typename Acc, int G>
+hipError_t allow_lds_r(int rows)
+{
+    if (rows == 1) return allow_lds<T, Acc, G, 1>();
+    if (rows == 2) return allow_lds<T, Acc, G, 2>();
+    return allow_lds<T, Acc, G, 4>();
 }
 
 template <typename T, typename Acc>
-void launch_step_g(int G, dim3 grid, hipStream_t st, const void* items, const int2* blocks, int s, int mode, int rows)
+void launch_step_g(int G, int kind, dim3 grid, hipStream_t st, const void* items, const int2* blocks, int s,
+                   int mode, int rows)
 {
-    if (G == 1) launch_step<T, Acc, 1>(grid, st, items, blocks, s, mode, rows);
-    else if (G == 2) launch_step<T, Acc, 2>(grid, st, items, blocks, s, mode, rows);
-    else launch_step<T, Acc, 4>(grid, st, items, blocks, s, mode, rows);
+    if (G == 1) launch_step<T, Acc, 1>(kind, grid, st, items, blocks, s, mode, rows);
+    else if (G == 2) launch_step<T, Acc, 2>(kind, grid, st, items, blocks, s, mode, rows);
+    else launch_step<T, Acc, 4>(kind, grid, st, items, blocks, s, mode, rows);
 }
 
-void step(fwi_plan* p, dim3 grid, hipStream_t st, const int2* blocks, int s, int mode)
+void step(fwi_plan* p, int kind, dim3 grid, hipStream_t st, const int2* blocks, int s, int mode)
 {
     if (p->dtype == FWI_F64)
-        launch_step_g<double, double>(p->G, grid, st, p->d_items, blocks, s, mode, p->rows);
+        launch_step_g<double, double>(p->G, kind, grid, st, p->d_items, blocks, s, mode, p->rows);
     else if (p->acc_double)
-        launch_step_g<float, double>(p->G, grid, st, p->d_items, blocks, s, mode, p->rows);
+        launch_step_g<float, double>(p->G, kind, grid, st, p->d_items, blocks, s, mode, p->rows);
     else
-        launch_step_g<float, float>(p->G, grid, st, p->d_items, blocks, s, mode, p->rows);
+        launch_step_g<float, float>(p->G, kind, grid, st, p->d_items, blocks, s, mode, p->rows);
+}
+
+hipError_t allow_lds_plan(const fwi_plan* p)
+{
+    if (p->S != 2) return hipSuccess;
+    auto pick = [&](auto t, auto a) -> hipError_t {
+        using T = decltype(t);
+        using A = decltype(a);
+        if (p->G == 1) return allow_lds_r<T, A, 1>(p->rows);
+        if (p->G == 2) return allow_lds_r<T, A, 2>(p->rows);
+        return allow_lds_r<T, A, 4>(p->rows);
+    };
+    if (p->dtype == FWI_F64) return pick(double(), double());
+    if (p->acc_double) return pick(float(), double());
+    return pick(float(), float());
+}
+
+// Launch kinds present in a wave at launch s of a call: bit k set when some
+// item needs kind k (host mirror of the device schedule).
+unsigned wave_kinds(const fwi_plan* p, const Wave& w, int s, int mode, int* n_active)
+{
+    const int S = p->S;
+    unsigned bits = 0;
+    *n_active = 0;
+    for (int pos = 0; pos < (int)w.items.size(); ++pos) {
+        const ItemPlan& it = p->items[w.items[pos]];
+        const unsigned before = bits;
+        const int T = p->media[it.medium].g.nt, K = it.K, J = it.J;
+        const int nf = (T + S - 1) / S;
+        int sl = mode == kRunAdjOnly ? s + nf : s;
+        bool active = false;
+        if (sl < nf) {
+            bits |= std::min(S, T - sl * S) == 2 ? 2u : 1u;
+            active = true;
+        } else if (mode != kRunFwdOnly) {
+            sl -= nf;
+            const int last = T - (J - 1) * K, nl = (last + S - 1) / S;
+            const int nk = (K + S - 1) / S;
+            if (sl < nl) {
+                bits |= std::min(S, last - sl * S) == 2 ? 8u : 4u;
+                active = true;
+            } else if (sl - nl < 2 * nk * (J - 1)) {
+                const int rem = (sl - nl) % (2 * nk);
+                const int m = rem < nk ? rem : rem - nk;
+                const bool two = std::min(S, K - m * S) == 2;
+                bits |= rem < nk ? (two ? 2u : 1u) : (two ? 8u : 4u);
+                active = true;
+            }
+        }
+        (void)before;
+        if (active) *n_active = pos + 1;
+    }
+    return bits;
 }
 
 int grid_for(int64_t n, int per_block, int cap)
@@ -244,9 +347,11 @@ static fwi_status create_impl(fwi_plan* p, fwi_dtype dtype, const fwi_grid* grid
         return fail(p, FWI_ERR_INVALID, "group must be 0, 1, 2 or 4");
     if (o.mode == FWI_PLAIN && o.group > 1) return fail(p, FWI_ERR_INVALID, "plain mode runs one transmit per item");
     if (o.rows < 0 || o.rows > 64) return fail(p, FWI_ERR_INVALID, "rows must be in [0, 64]");
+    if (o.steps_per_launch < 0 || o.steps_per_launch > 2) return fail(p, FWI_ERR_INVALID, "steps_per_launch must be 0, 1 or 2");
     if (o.ckpt_interval < 0) return fail(p, FWI_ERR_INVALID, "ckpt_interval must be >= 0");
     if (o.mem_budget < 0) return fail(p, FWI_ERR_INVALID, "mem_budget must be >= 0");
     if (o.use_graph && o.mode != FWI_BATCHED) return fail(p, FWI_ERR_INVALID, "use_graph requires FWI_BATCHED");
+    if (o.forward_only != 0 && o.forward_only != 1) return fail(p, FWI_ERR_INVALID, "forward_only must be 0 or 1");
     for (int i = 0; i < n_media; ++i) {
         std::string msg;
         fwi_status st = validate_grid(grids[i], i, msg);
@@ -256,7 +361,18 @@ static fwi_status create_impl(fwi_plan* p, fwi_dtype dtype, const fwi_grid* grid
     p->dtype = dtype;
     p->opt = o;
     p->G = o.group ? o.group : (o.mode == FWI_PLAIN ? 1 : 4);
-    p->rows = o.rows ? o.rows : 4;
+    // default: two steps per launch on 64 x 8 tiles (one step on 64 x 16 for the plain form)
+    p->S = o.steps_per_launch ? o.steps_per_launch : (o.mode == FWI_PLAIN ? 1 : 2);
+    p->rows = o.rows ? o.rows : (p->S == 2 ? 2 : 4);
+    if (p->S == 2 && p->rows != 1 && p->rows != 2 && p->rows != 4)
+        return fail(p, FWI_ERR_INVALID, "two steps per launch need rows of 1, 2 or 4");
+    if (p->S == 2) {
+        // LDS of the two-step adjoint: tile + 2 (fields, q, bt) and three tile + 1 field planes
+        const size_t n0 = (size_t)(kTileX + 4) * (kWavesZ * p->rows + 4), n1 = (size_t)(kTileX + 2) * (kWavesZ * p->rows + 2);
+        const size_t ts = dtype == FWI_F64 ? 8 : 4;
+        if ((n0 * (p->G + 2) + 3 * n1 * p->G) * ts > kLdsBytes)
+            return fail(p, FWI_ERR_INVALID, "two-step tile does not fit the 160 KiB of LDS: use fewer rows");
+    }
     p->acc_double = dtype == FWI_F64 || o.acc_double;
     p->tsize = dtype == FWI_F64 ? 8 : 4;
     p->asize = p->acc_double ? 8 : 4;
@@ -302,8 +418,8 @@ static fwi_status create_impl(fwi_plan* p, fwi_dtype dtype, const fwi_grid* grid
     };
     auto state_bytes = [&](const ItemPlan& it, int K) {
         const int T = p->media[it.medium].g.nt;
-        const int J = (T + K - 1) / K;
-        return plane_bytes(it) * (size_t)(K + 2 * (J - 1) + 2);
+        const int J = o.forward_only ? 1 : (T + K - 1) / K;
+        return plane_bytes(it) * (size_t)(K + 2 * (J - 1) + 4);
     };
     auto auto_k = [&](int T) {
         if (T <= 2) return T;
@@ -313,7 +429,8 @@ static fwi_status create_impl(fwi_plan* p, fwi_dtype dtype, const fwi_grid* grid
     for (auto& it : p->items) {
         const int T = p->media[it.medium].g.nt;
         int K;
-        if (o.ckpt_interval == 0) K = auto_k(T);
+        if (o.forward_only) K = 4;       // rolling buffer of four planes, no replay
+        else if (o.ckpt_interval == 0) K = auto_k(T);
         else if (o.ckpt_interval >= T) K = T;
         else K = std::max(2, o.ckpt_interval);
         if (T == 1) K = 1;
@@ -329,6 +446,8 @@ static fwi_status create_impl(fwi_plan* p, fwi_dtype dtype, const fwi_grid* grid
                      align_up((size_t)2 * m.g.nx * m.g.nz * p->tsize);
     }
     const double state_budget = budget - (double)fixed;
+    if (o.forward_only)
+        for (auto& it : p->items) it.J = 1;
     const int n_items = (int)p->items.size();
     if (o.mode == FWI_PLAIN) {
         // items run one after another and share one state slot
@@ -386,10 +505,17 @@ static fwi_status create_impl(fwi_plan* p, fwi_dtype dtype, const fwi_grid* grid
             if (!w.items.empty()) p->waves.push_back(w);
         }
     }
+    // two steps per launch read and write four field planes of the segment
+    // buffer at once: that needs K >= 4 wherever the buffer wraps
+    if (p->S == 2)
+        for (auto& it : p->items)
+            if (it.K < 4 && it.K < p->media[it.medium].g.nt) p->S = 1;
+    p->nlam = p->S == 2 ? 4 : 2;
     for (auto& it : p->items) {
         const int T = p->media[it.medium].g.nt;
-        it.J = (T + it.K - 1) / it.K;
-        it.steps = 2 * T + it.K * (it.J - 1);
+        it.J = o.forward_only ? 1 : (T + it.K - 1) / it.K;
+        const int S = p->S, last = T - (it.J - 1) * it.K;
+        it.steps = (T + S - 1) / S + (last + S - 1) / S + 2 * ((it.K + S - 1) / S) * (it.J - 1);
         const MediumPlan& m = p->media[it.medium];
         p->recompute_updates += (int64_t)it.K * (it.J - 1) * m.g.nx * m.g.nz * it.g_used;
     }
@@ -417,7 +543,7 @@ static fwi_status create_impl(fwi_plan* p, fwi_dtype dtype, const fwi_grid* grid
     for (auto& w : p->waves) {
         size_t o2 = state_off;
         w.lam_off = o2;
-        for (int i : w.items) { p->items[i].lam_off = o2; o2 += 2 * plane_bytes(p->items[i]); }
+        for (int i : w.items) { p->items[i].lam_off = o2; o2 += (size_t)p->nlam * plane_bytes(p->items[i]); }
         w.lam_bytes = o2 - w.lam_off;
         for (int i : w.items) { p->items[i].ck_off = o2; o2 += plane_bytes(p->items[i]) * 2 * (size_t)(p->items[i].J - 1); }
         for (int i : w.items) { p->items[i].seg_off = o2; o2 += plane_bytes(p->items[i]) * (size_t)p->items[i].K; }
@@ -425,10 +551,10 @@ static fwi_status create_impl(fwi_plan* p, fwi_dtype dtype, const fwi_grid* grid
         w.steps = w.fwd = w.adj = 0;
         for (int i : w.items) {
             const ItemPlan& it = p->items[i];
-            const int T = p->media[it.medium].g.nt;
+            const int nf = (p->media[it.medium].g.nt + p->S - 1) / p->S;
             w.steps = std::max(w.steps, it.steps);
-            w.fwd = std::max(w.fwd, T);
-            w.adj = std::max(w.adj, it.steps - T);
+            w.fwd = std::max(w.fwd, nf);
+            w.adj = std::max(w.adj, it.steps - nf);
         }
     }
     off += state_max;
@@ -494,14 +620,66 @@ static fwi_status create_impl(fwi_plan* p, fwi_dtype dtype, const fwi_grid* grid
         }
         it.tile_off_off = tab_put(toff.data(), toff.size() * 4);
         it.entry_off = tab_put(ent.data(), ent.size() * sizeof(Entry));
-    }
-    for (auto& w : p->waves) {
-        w.blk0 = (int)p->blocks.size();
-        for (int i : w.items) {
-            ItemPlan& it = p->items[i];
-            it.blk0 = (int)p->blocks.size();
-            for (int t = 0; t < it.n_tiles; ++t) p->blocks.push_back(make_int2(i, t));
+        // the same receivers listed for every tile whose region grown by one cell holds them
+        std::vector<Raw> rx;
+        for (const Raw& r0 : raw) {
+            const int cell = r0.slot / G, ix = cell % m.g.nx, iz = cell / m.g.nx;
+            for (int tz = std::max(0, (iz - 1) / tile_rows); tz <= std::min(it.tiles_z - 1, (iz + 1) / tile_rows); ++tz)
+                for (int tx = std::max(0, (ix - 1) / kTileX); tx <= std::min(it.tiles_x - 1, (ix + 1) / kTileX); ++tx) {
+                    const int xa = tx * kTileX - 1, xb = tx * kTileX + kTileX;
+                    const int za = tz * tile_rows - 1, zb = tz * tile_rows + tile_rows;
+                    if (ix >= xa && ix <= xb && iz >= za && iz <= zb)
+                        rx.push_back({tz * it.tiles_x + tx, r0.slot, r0.trace_off, r0.order});
+                }
         }
+        std::stable_sort(rx.begin(), rx.end(), [](const Raw& a, const Raw& b) {
+            return a.tile != b.tile ? a.tile < b.tile : (a.slot != b.slot ? a.slot < b.slot : a.order < b.order);
+        });
+        std::vector<int32_t> toffx(it.n_tiles + 1, 0);
+        std::vector<Entry> entx(rx.size());
+        for (size_t k = 0; k < rx.size(); ++k) {
+            toffx[rx[k].tile + 1]++;
+            entx[k] = {rx[k].slot, rx[k].trace_off, 0, 0};
+        }
+        for (int t = 0; t < it.n_tiles; ++t) toffx[t + 1] += toffx[t];
+        for (size_t k = 0; k < entx.size();) {
+            size_t e = k;
+            while (e < entx.size() && rx[e].tile == rx[k].tile && entx[e].slot == entx[k].slot) ++e;
+            entx[k].run = (int32_t)(e - k);
+            k = e;
+        }
+        it.tile_off_x_off = tab_put(toffx.data(), toffx.size() * 4);
+        it.entry_x_off = tab_put(entx.data(), entx.size() * sizeof(Entry));
+    }
+    // XCD-aware block table: workgroups are dealt to the XCDs round-robin by
+    // block index, so block 8j + k runs on XCD k.  Each item's tiles are cut
+    // into kXcd contiguous runs (row-major tile order) and run k is dealt to
+    // XCD k, so the halo rows and columns shared by neighbouring tiles are
+    // fetched into one L2 instead of several.  Unused slots hold item -1.
+    // Items of a wave are ordered longest schedule first, so that the items
+    // still active at a late launch own a prefix of the wave's blocks and the
+    // launch grid can stop there.
+    for (auto& w : p->waves) {
+        std::stable_sort(w.items.begin(), w.items.end(),
+                         [&](int a2, int b2) { return p->items[a2].steps > p->items[b2].steps; });
+        w.blk0 = (int)p->blocks.size();
+        std::vector<std::vector<int2>> per(kXcd);
+        w.prefix.assign(1, 0);
+        for (int i : w.items) {
+            const ItemPlan& it = p->items[i];
+            size_t rows_needed = 0;
+            for (int k = 0; k < kXcd; ++k) {
+                const int t0 = (int)((int64_t)it.n_tiles * k / kXcd), t1 = (int)((int64_t)it.n_tiles * (k + 1) / kXcd);
+                for (int t = t0; t < t1; ++t) per[k].push_back(make_int2(i, t));
+                rows_needed = std::max(rows_needed, per[k].size());
+            }
+            w.prefix.push_back((int)(rows_needed * kXcd));
+        }
+        size_t len = 0;
+        for (auto& v : per) len = std::max(len, v.size());
+        for (size_t j = 0; j < len; ++j)
+            for (int k = 0; k < kXcd; ++k)
+                p->blocks.push_back(j < per[k].size() ? per[k][j] : make_int2(-1, 0));
         w.nblk = (int)p->blocks.size() - w.blk0;
     }
     const size_t blocks_off = tab_put(p->blocks.data(), p->blocks.size() * sizeof(int2));
@@ -522,6 +700,7 @@ static fwi_status create_impl(fwi_plan* p, fwi_dtype dtype, const fwi_grid* grid
     p->d_media = base + media_off;
     p->d_status = reinterpret_cast<unsigned*>(base + status_off);
     HIPCHK(p, hipHostMalloc(&p->h_stage, align_up(p->item_bytes) + align_up(p->media_bytes), hipHostMallocDefault));
+    HIPCHK(p, allow_lds_plan(p));
     HIPCHK(p, hipEventCreateWithFlags(&p->stage_ev, hipEventDisableTiming));
     return FWI_OK;
 }
@@ -576,6 +755,7 @@ extern "C" fwi_status fwi_plan_get_info(const fwi_plan* p, fwi_plan_info* info)
     for (auto& w : p->waves) l += w.steps;
     info->launches = (int32_t)std::min<int64_t>(l, INT32_MAX);
     info->waves = (int32_t)p->waves.size();
+    info->steps_per_launch = p->S;
     info->max_ckpt = 0;
     info->min_ckpt = INT32_MAX;
     for (auto& it : p->items) {
@@ -624,6 +804,10 @@ void fill_descriptors(fwi_plan* p, const fwi_io* io, unsigned char* ws, bool adj
         d.d_adj = reinterpret_cast<const T*>(mio.d_adj);
         d.tile_off = reinterpret_cast<const int32_t*>(tabs + ip.tile_off_off);
         d.entries = reinterpret_cast<const Entry*>(tabs + ip.entry_off);
+        d.tile_off_x = reinterpret_cast<const int32_t*>(tabs + ip.tile_off_x_off);
+        d.entries_x = reinterpret_cast<const Entry*>(tabs + ip.entry_x_off);
+        d.S = p->S;
+        d.nlam = p->nlam;
         items[i] = d;
     }
     for (size_t i = 0; i < p->media.size(); ++i) {
@@ -692,7 +876,13 @@ void enqueue_sequence(fwi_plan* p, hipStream_t st, unsigned char* ws, int call, 
     for (const Wave& w : p->waves) {
         const int S = call == kExecute ? w.steps : call == kForward ? w.fwd : w.adj;
         if (call != kForward) zero_bytes(st, ws + w.lam_off, w.lam_bytes);
-        for (int s = 0; s < S; ++s) step(p, dim3(w.nblk), st, p->d_blocks + w.blk0, s, mode);
+        for (int s = 0; s < S; ++s) {
+            int n_active = 0;
+            const unsigned kinds = wave_kinds(p, w, s, mode, &n_active);
+            const dim3 grid((unsigned)w.prefix[n_active]);
+            for (int k = 0; k < 4; ++k)
+                if (kinds & (1u << k)) step(p, k, grid, st, p->d_blocks + w.blk0, s, mode);
+        }
     }
     if (call != kAdjoint) medium_kernels(p, st, 1, ws);
     if (call != kForward) medium_kernels(p, st, 2, ws);
@@ -719,6 +909,8 @@ fwi_status run_call(fwi_plan* p, const fwi_io* io, void* workspace, size_t bytes
             else if (dadj != (m.d_adj != nullptr)) return fail(p, FWI_ERR_INVALID, "d_adj must be given for all media or none");
         }
     }
+    if (p->opt.forward_only && (want_grad || call == kAdjoint))
+        return fail(p, FWI_ERR_INVALID, "forward-only plan: no adjoint or gradient");
     if (call == kAdjoint && p->fwd_ws != workspace) return fail(p, FWI_ERR_STATE, "no forward state in this workspace");
     if (call != kExecute && p->waves.size() > 1)
         return fail(p, FWI_ERR_INVALID, "forward/adjoint need every item resident at once: use FWI_BATCHED "

@@ -101,6 +101,8 @@ def _grid(**kw):
     ({}, dict(mode="plain", group=4), 1),
     ({}, dict(rows=100), 1),
     ({}, dict(mode="plain", use_graph=True), 1),
+    ({}, dict(steps_per_launch=2, rows=3), 1),
+    ({}, dict(steps_per_launch=3), 1),
 ])
 def test_host_validation(kw, opt, code):
     with pytest.raises(F.FwiError) as e:

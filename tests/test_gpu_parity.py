@@ -140,3 +140,87 @@ def test_rodgauss512_full_size_subset():
     ref = oracle_grad(m, obs, ckpt=89)
     res, plan = gpu_run([m], [obs], dtype="f32")
     _check(res[0], ref, "f32")
+
+
+# ---------------------------------------------------------------- two steps per launch
+
+def _seam_medium(seed, nt=151, n_tx=3):
+    """Receivers and sources on tile seams (x 63/64, z 15/16 for 16-row tiles)
+    and on the border, with a duplicate receiver; odd step count."""
+    m = W.small_random_medium(seed, 140, 70, nt, n_tx=n_tx, n_rcv=8, npml=4, courant=0.5)
+    g = m.geom
+    nx = g.nx
+    cells = [15 * nx + 63, 16 * nx + 64, 15 * nx + 64, 16 * nx + 63, 0 * nx + 64, 31 * nx + 128, 47 * nx + 139,
+             15 * nx + 63]
+    for p in range(g.n_tx):
+        g.rcv[p, :] = np.roll(np.array(cells, np.int32), p)
+    g.src[0] = 16 * nx + 64
+    if g.n_tx > 1:
+        g.src[1] = 32 * nx + 63
+    return m
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("ckpt,rows", [(0, 2), (9, 2), (10**6, 1), (7, 1), (5, 4)])
+def test_two_step_launches(dtype, ckpt, rows):
+    if dtype == "f64" and rows == 4:
+        pytest.skip("the FP64 two-step tile of 16 rows exceeds the LDS of a compute unit")
+    m = _seam_medium(31)
+    obs = _observed(m, 4)
+    ref = oracle_grad(m, obs)
+    res, plan = gpu_run([m], [obs], dtype=dtype, ckpt=ckpt, rows=rows, steps_per_launch=2)
+    assert plan.info["steps_per_launch"] == 2
+    _check(res[0], ref, dtype)
+
+
+def test_two_step_matches_one_step():
+    """FP64: fusing two steps per launch changes nothing beyond rounding."""
+    m = _seam_medium(32, nt=120, n_tx=5)
+    obs = _observed(m, 5)
+    one, _ = gpu_run([m], [obs], dtype="f64", ckpt=8, steps_per_launch=1)
+    two, _ = gpu_run([m], [obs], dtype="f64", ckpt=8, steps_per_launch=2)
+    for k in ("traces", "grad_c", "grad_rho"):
+        assert rel_l2(two[0][k], one[0][k]) <= 1e-13, k
+
+
+def test_two_step_checkpoint_bitwise():
+    m = W.small_random_medium(33, 97, 70, 121, n_tx=4, n_rcv=6, npml=3)
+    obs = _observed(m, 6)
+    outs = []
+    for K in (10**6, 9, 5):
+        res, plan = gpu_run([m], [obs], dtype="f32", ckpt=K, steps_per_launch=2)
+        outs.append(res[0])
+    for o in outs[1:]:
+        for k in ("traces", "grad_c", "grad_rho", "misfit"):
+            assert np.array_equal(o[k], outs[0][k]), k
+
+
+def test_two_step_uneven_and_split():
+    import oracle
+    media = [_seam_medium(34, nt=101, n_tx=5), W.small_random_medium(35, 90, 66, 80, n_tx=2, n_rcv=4, npml=3)]
+    obs = [_observed(m, 30 + i) for i, m in enumerate(media)]
+    res, plan = gpu_run(media, obs, dtype="f32", ckpt=6, steps_per_launch=2)
+    for m, o, r in zip(media, obs, res):
+        _check(r, oracle_grad(m, o), "f32")
+    rng = np.random.default_rng(10)
+    ys = [rng.standard_normal((m.geom.n_tx, m.geom.nt, m.geom.n_rcv)) for m in media]
+    res, plan = gpu_run(media, None, dtype="f64", d_adj_list=ys, ckpt=6, steps_per_launch=2)
+    for m, y, r in zip(media, ys, res):
+        ref = oracle.run(m.geom, m.c, m.rho, m.wavelet, d_adj=y)
+        assert rel_l2(r["grad_c"], ref["grad_c"]) <= 1e-10
+        assert rel_l2(r["grad_rho"], ref["grad_rho"]) <= 1e-10
+
+
+@pytest.mark.parametrize("spl", [1, 2])
+def test_forward_only_plan(spl):
+    """A forward-only plan (rolling four-plane buffer, no replay) gives
+    bitwise the traces and misfit of a full plan and refuses gradients."""
+    import paper_2603_04070_amd as F
+    media = [_seam_medium(36, nt=97, n_tx=5), W.small_random_medium(37, 90, 66, 61, n_tx=2, n_rcv=4, npml=3)]
+    obs = [_observed(m, 40 + i) for i, m in enumerate(media)]
+    full, _ = gpu_run(media, obs, dtype="f32", ckpt=10**6, steps_per_launch=spl)
+    fo, plan = gpu_run(media, [None, None], dtype="f32", forward_only=True, steps_per_launch=spl)
+    for a, b in zip(full, fo):
+        assert np.array_equal(a["traces"], b["traces"])
+    with pytest.raises(F.FwiError):
+        gpu_run(media, obs, dtype="f32", forward_only=True, steps_per_launch=spl)
