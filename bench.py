@@ -42,6 +42,9 @@ def parse():
     ap.add_argument("--ckpt", type=int, default=0)
     ap.add_argument("--graph", type=int, default=0)
     ap.add_argument("--spl", type=int, default=0, help="time steps fused per launch (0: library default)")
+    ap.add_argument("--persistent", type=int, default=0, help="one persistent launch per wave")
+    ap.add_argument("--tune", type=int, default=1, help="pick steps per launch and tile rows with the autotuner")
+    ap.add_argument("--tune-cache", default="", help="JSON cache file of the autotuner")
     ap.add_argument("--mem-frac", type=float, default=0.85, help="workspace budget as a fraction of free HBM")
     ap.add_argument("--plain-media", type=int, default=1, help="media of the workload timed in plain form (0: skip)")
     ap.add_argument("--cpu-baseline", type=int, default=1)
@@ -85,8 +88,9 @@ def make_plan(media, dtype, mode, args, c_max, forward_only=False):
     torch.cuda.empty_cache()
     free, _ = torch.cuda.mem_get_info()
     return F.Plan(grids, dtype=dtype, mode=mode, ckpt=args.ckpt, group=args.group if mode == "batched" else 0,
-                  rows=args.rows, use_graph=bool(args.graph) and mode == "batched",
+                  rows=args.rows if mode == "batched" else 0, use_graph=bool(args.graph) and mode == "batched",
                   steps_per_launch=args.spl if mode == "batched" else 1, forward_only=forward_only,
+                  persistent=bool(args.persistent) and mode == "batched" and not forward_only,
                   mem_budget=args.mem_frac * free)
 
 
@@ -162,6 +166,13 @@ def main():
     d_obs = observed(partners, dtype, args, c_max, dev)
     mdev = to_dev(media, dtype, dev)
 
+    tuned = None
+    if args.tune and args.rows == 0 and args.spl == 0:
+        grids = [F.GridSpec.of(m.geom, c_max) for m in media]
+        t0 = time.perf_counter()
+        tuned = F.autotune(grids, dtype=dtype, mode=args.mode, group=args.group, cache=args.tune_cache or None)
+        tuned["seconds"] = round(time.perf_counter() - t0, 2)
+        args.rows, args.spl = tuned["rows"], tuned["steps_per_launch"]
     plan = make_plan(media, dtype, args.mode, args, c_max)
     info = plan.info
     ms, _ = time_gradient(plan, mdev, d_obs, dtype, args.steps, args.warmup, dev)
@@ -219,6 +230,8 @@ def main():
             "mode": args.mode,
             "group": info["group"], "rows": info["rows"], "waves": info["waves"],
             "steps_per_launch": info["steps_per_launch"],
+            "persistent": bool(args.persistent), "graph": bool(args.graph),
+            "autotuned": tuned,
             "ckpt_min": info["min_ckpt"], "ckpt_max": info["max_ckpt"],
             "launches_per_step": launches,
             "workspace_gib": round(info["workspace_bytes"] / 2 ** 30, 2),

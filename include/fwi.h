@@ -107,6 +107,11 @@ typedef struct fwi_options {
                              /*    K < 4; with 2, rows must be 1, 2 or 4 (FP64: 1 or 2)           */
     int32_t forward_only;    /* 1: traces and misfit only; no replay state is kept and           */
                              /*    gradient or adjoint calls return FWI_ERR_INVALID              */
+    int32_t persistent;      /* 1: one launch per wave runs every step, its workgroups meeting   */
+                             /*    at a device-wide barrier between steps (FWI_BATCHED only)     */
+    int32_t barrier_spin;    /* polls before a barrier wait is abandoned (0 = 2^21); an         */
+                             /*    abandoned wait ends the launch and fwi_plan_check reports     */
+                             /*    FWI_ERR_HIP                                                   */
     double mem_budget;       /* bytes the workspace may use; 0 = 60% of free device memory      */
     const char *tune_cache;  /* JSON cache path of the tile autotuner, or NULL                   */
 } fwi_options;
@@ -165,6 +170,18 @@ fwi_status fwi_plan_adjoint(fwi_plan *plan, const fwi_io *io, void *workspace,
 fwi_status fwi_plan_check(fwi_plan *plan);
 
 void fwi_plan_destroy(fwi_plan *plan);
+
+/* Autotuner: pick steps_per_launch and rows for these grids by timing short
+ * device probes of every feasible candidate (the grids' schedules cut to 24
+ * steps, every plane kept, a homogeneous medium) and keeping the fastest per
+ * cell-update.  *out receives *base (or the defaults when base is NULL)
+ * with those two fields set; *ns_per_update (optional) the probe's time.
+ * When base->tune_cache names a file, a cached choice for the same GPU
+ * architecture, dtype, mode, group and size class is reused and new choices
+ * are stored there (small JSON object).  Allocates and frees its own device
+ * buffers and synchronises; call it before fwi_plan_create, off the hot path. */
+fwi_status fwi_autotune(fwi_dtype dtype, const fwi_grid *grids, int32_t n_media, const fwi_options *base,
+                        fwi_options *out, double *ns_per_update);
 
 /* Static description of a status code. */
 const char *fwi_status_string(fwi_status status);

@@ -19,7 +19,7 @@ import numpy as np
 
 from . import _abi
 
-__all__ = ["GridSpec", "FwiError", "Plan", "gradient", "forward"]
+__all__ = ["GridSpec", "FwiError", "Plan", "gradient", "forward", "autotune"]
 
 
 class FwiError(RuntimeError):
@@ -92,7 +92,7 @@ class Plan:
     def __init__(self, grids: Sequence[GridSpec], dtype: str = "f32", mode: str = "batched",
                  ckpt: int = 0, group: int = 0, rows: int = 0, use_graph: bool = False,
                  acc_double: bool = False, mem_budget: float = 0.0, steps_per_launch: int = 0,
-                 forward_only: bool = False):
+                 forward_only: bool = False, persistent: bool = False, barrier_spin: int = 0):
         lib = _lib()
         self.grids = list(grids)
         self.dtype = dtype
@@ -115,6 +115,8 @@ class Plan:
         opt.acc_double = int(bool(acc_double))
         opt.steps_per_launch = int(steps_per_launch)
         opt.forward_only = int(bool(forward_only))
+        opt.persistent = int(bool(persistent))
+        opt.barrier_spin = int(barrier_spin)
         opt.mem_budget = float(mem_budget)
         self._h = C.c_void_p()
         dt = _abi.FWI_F64 if dtype == "f64" else _abi.FWI_F32
@@ -177,6 +179,38 @@ class Plan:
         import torch
         n = (self.workspace_bytes + 255) // 256 * 256
         return torch.empty(n, dtype=torch.uint8, device=device)
+
+
+def _grid_array(grids, keep):
+    arr = (_abi.FwiGrid * len(grids))()
+    for i, g in enumerate(grids):
+        src = np.ascontiguousarray(g.src, np.int32)
+        rcv = np.ascontiguousarray(g.rcv, np.int32)
+        keep += [src, rcv]
+        arr[i] = _abi.FwiGrid(g.nx, g.nz, g.nt, g.npml, g.h, g.dt, g.pml_r, g.pml_cref, g.c_max,
+                              len(src), rcv.shape[1], src.ctypes.data, rcv.ctypes.data)
+    return arr
+
+
+def autotune(grids: Sequence[GridSpec], dtype: str = "f32", mode: str = "batched", group: int = 0,
+             cache: Optional[str] = None) -> dict:
+    """Time short device probes of the kernel variants for these grids and
+    return the fastest ``steps_per_launch`` and ``rows`` (fwi_autotune)."""
+    lib = _lib()
+    keep = []
+    arr = _grid_array(list(grids), keep)
+    base = _abi.FwiOptions()
+    base.mode = _abi.FWI_PLAIN if mode == "plain" else _abi.FWI_BATCHED
+    base.group = int(group)
+    cache_b = cache.encode() if cache else None
+    base.tune_cache = cache_b
+    out = _abi.FwiOptions()
+    ns = C.c_double()
+    dt = _abi.FWI_F64 if dtype == "f64" else _abi.FWI_F32
+    st = lib.fwi_autotune(dt, arr, len(grids), C.byref(base), C.byref(out), C.byref(ns))
+    if st != _abi.FWI_OK:
+        raise FwiError(st, lib.fwi_last_create_error().decode())
+    return {"steps_per_launch": out.steps_per_launch, "rows": out.rows, "ns_per_update": ns.value}
 
 
 def _torch_dtype(dtype):

@@ -17,7 +17,7 @@ FWI_PLAIN, FWI_BATCHED = 0, 1
 EXPORTS = (
     "fwi_plan_create", "fwi_plan_workspace_size", "fwi_plan_get_info", "fwi_plan_execute",
     "fwi_plan_forward", "fwi_plan_adjoint", "fwi_plan_check", "fwi_plan_destroy",
-    "fwi_status_string", "fwi_plan_last_error", "fwi_last_create_error",
+    "fwi_status_string", "fwi_plan_last_error", "fwi_last_create_error", "fwi_autotune",
 )
 
 
@@ -45,6 +45,7 @@ class FwiOptions(C.Structure):
         ("mode", C.c_int32), ("ckpt_interval", C.c_int32), ("group", C.c_int32),
         ("rows", C.c_int32), ("use_graph", C.c_int32), ("acc_double", C.c_int32),
         ("steps_per_launch", C.c_int32), ("forward_only", C.c_int32),
+        ("persistent", C.c_int32), ("barrier_spin", C.c_int32),
         ("mem_budget", C.c_double),
         ("tune_cache", C.c_char_p),
     ]
@@ -71,6 +72,13 @@ def load():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it first (__graft_entry__.build())")
+    # torch ships its own HIP runtime under the same soname as /opt/rocm's; load
+    # torch first so that libfwi binds to the runtime torch's tensors and
+    # streams live in (one HIP runtime per process)
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = C.CDLL(LIB_PATH)
     P = C.c_void_p
     lib.fwi_plan_create.argtypes = [C.POINTER(P), C.c_int, C.POINTER(FwiGrid), C.c_int32, C.POINTER(FwiOptions)]
@@ -85,6 +93,9 @@ def load():
     lib.fwi_status_string.restype = C.c_char_p
     lib.fwi_plan_last_error.argtypes = [P]
     lib.fwi_plan_last_error.restype = C.c_char_p
+    lib.fwi_autotune.argtypes = [C.c_int, C.POINTER(FwiGrid), C.c_int32, C.POINTER(FwiOptions),
+                                 C.POINTER(FwiOptions), C.POINTER(C.c_double)]
+    lib.fwi_autotune.restype = C.c_int
     lib.fwi_last_create_error.argtypes = []
     lib.fwi_last_create_error.restype = C.c_char_p
     for name in ("fwi_plan_create", "fwi_plan_workspace_size", "fwi_plan_get_info", "fwi_plan_execute",

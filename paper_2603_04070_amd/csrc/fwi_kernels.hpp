@@ -40,7 +40,7 @@ enum Phase : int { kIdle = 0, kFwd = 1, kRecomp = 2, kAdj = 3 };
 enum RunMode : int { kRunAll = 0, kRunFwdOnly = 1, kRunAdjOnly = 2 };
 
 // Status bits raised on the device.
-enum : unsigned { kFlagCfl = 1u, kFlagMedium = 2u, kFlagNonfinite = 4u };
+enum : unsigned { kFlagCfl = 1u, kFlagMedium = 2u, kFlagNonfinite = 4u, kFlagBarrier = 8u };
 
 // One receiver entry of a tile: field slot cell*G + g, and the offset of
 // trace (transmit, receiver) sample 0 in the medium's trace array.
@@ -317,7 +317,11 @@ __device__ __forceinline__ void inject_tile(const Item<T, Acc>& it, int tile, in
 
 // Forward-type step (FWD or RECOMP) on one tile, straight from global memory:
 // each lane marches ``rows`` rows keeping the vertical neighbours in registers.
-template <typename T, int G, typename Acc>
+// V distinguishes the persistent kernel's copy of a tile routine from the
+// per-step kernels' copy: each instantiation keeps one caller and is inlined
+// there by the ordinary inliner, so the per-step kernels' code is unaffected
+// by the persistent form.
+template <typename T, int G, typename Acc, int V = 0>
 __device__ void tile_forward(const Item<T, Acc>& it, const Step& st, int tile_x, int tile_z, int rows, bool sample)
 {
     const int nx = it.nx, nz = it.nz, n = st.n;
@@ -370,7 +374,7 @@ __device__ void tile_forward(const Item<T, Acc>& it, const Step& st, int tile_x,
 }
 
 // Adjoint step at time t on one tile, with the imaging of lam^t and u^{t-1}.
-template <typename T, int G, typename Acc>
+template <typename T, int G, typename Acc, int V = 0>
 __device__ void tile_adjoint(const Item<T, Acc>& it, const Step& st, int tile_x, int tile_z, int rows)
 {
     const int nx = it.nx, nz = it.nz, t = st.n;
@@ -473,7 +477,7 @@ __device__ __forceinline__ void cell_of(int c, int grow, int x0, int z0, int& ix
     iz = z0 - grow + c / W;
 }
 
-template <typename T, int G, typename Acc, int R>
+template <typename T, int G, typename Acc, int R, int V = 0>
 __device__ void tile_forward2(const Item<T, Acc>& it, const Step& st, int tile_x, int tile_z, bool sample,
                               unsigned char* smem)
 {
@@ -592,7 +596,7 @@ __device__ void tile_forward2(const Item<T, Acc>& it, const Step& st, int tile_x
     if (sample) sample_tile(it, tile_z * it.tiles_x + tile_x, n, out1, out2);
 }
 
-template <typename T, int G, typename Acc, int R>
+template <typename T, int G, typename Acc, int R, int V = 0>
 __device__ void tile_adjoint2(const Item<T, Acc>& it, const Step& st, int tile_x, int tile_z, unsigned char* smem)
 {
     using L = Lds2<T, G, R, true>;
@@ -834,6 +838,85 @@ __global__ __launch_bounds__(kBlock) void adj2_kernel(const Item<T, Acc>* __rest
     tile_adjoint2<T, G, Acc, R>(it, st, bt.y % it.tiles_x, bt.y / it.tiles_x, smem);
 }
 
+// ---------------------------------------------------------------- persistent form
+//
+// One launch runs every step of a wave: each workgroup walks its share of
+// the launch's blocks (block b on workgroup b mod grid, so the XCD dealing
+// of the block table is kept when the grid is a multiple of 8), then all
+// workgroups meet at a grid barrier before the next step.  The grid never
+// exceeds what is co-resident.  The barrier is bounded: a workgroup that
+// polls spin_limit times without the barrier opening raises the abort
+// word, every workgroup then leaves, and the host reports the failure.
+
+// bar[0]: arrivals, bar[1]: generation, bar[2]: abort.
+__device__ __forceinline__ bool grid_sync(unsigned* bar, unsigned nblocks, unsigned spin_limit)
+{
+    __shared__ unsigned ok;
+    __syncthreads();
+    if (threadIdx.x == 0 && threadIdx.y == 0) {
+        bool good = true;
+        const unsigned g = __hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+        __threadfence();
+        const unsigned a = __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        if (a + 1 == nblocks) {
+            __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_add(&bar[1], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            unsigned polls = 0;
+            // relaxed polls (an acquire per poll would invalidate this XCD's L2 each
+            // time under the feet of workgroups still computing); the fence below
+            // is the acquire
+            while (__hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g) {
+                if (__hip_atomic_load(&bar[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u ||
+                    ++polls > spin_limit) {
+                    good = false;
+                    __hip_atomic_store(&bar[2], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(2);
+            }
+        }
+        __threadfence();
+        ok = good ? 1u : 0u;
+    }
+    __syncthreads();
+    return ok != 0u;
+}
+
+template <typename T, int G, typename Acc, int R>
+__global__ __launch_bounds__(kBlock) void persistent_kernel(const Item<T, Acc>* __restrict__ items,
+                                                             const int2* __restrict__ blocks,
+                                                             const int* __restrict__ nblk, int n_launch, int mode,
+                                                             int rows, unsigned* bar, unsigned spin_limit,
+                                                             unsigned* status)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    for (int s = 0; s < n_launch; ++s) {
+        const int nb = nblk[s];
+        for (int b = blockIdx.x; b < nb; b += gridDim.x) {
+            const int2 bt = blocks[b];
+            if (bt.x >= 0) {
+                const Item<T, Acc>& it = items[bt.x];
+                const Step st = item_step(it, s, mode);
+                const int tx = bt.y % it.tiles_x, tz = bt.y / it.tiles_x;
+                if (st.phase == kFwd || st.phase == kRecomp) {
+                    const bool smp = st.phase == kFwd && it.sample;
+                    if (st.count == 2) tile_forward2<T, G, Acc, R, 1>(it, st, tx, tz, smp, smem);
+                    else tile_forward<T, G, Acc, 1>(it, st, tx, tz, rows, smp);
+                } else if (st.phase == kAdj) {
+                    if (st.count == 2) tile_adjoint2<T, G, Acc, R, 1>(it, st, tx, tz, smem);
+                    else tile_adjoint<T, G, Acc, 1>(it, st, tx, tz, rows);
+                }
+            }
+            __syncthreads();   // LDS is reused by this workgroup's next block
+        }
+        if (s + 1 < n_launch && !grid_sync(bar, gridDim.x, spin_limit)) {
+            if (threadIdx.x == 0 && threadIdx.y == 0) atomicOr(status, kFlagBarrier);
+            return;
+        }
+    }
+}
+
 // ---------------------------------------------------------------- medium prep
 
 template <typename T>
@@ -899,6 +982,15 @@ __global__ void zero_kernel(T* __restrict__ p, int64_t n)
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x)
         p[i] = T(0);
+}
+
+// Fill n elements with v (synthetic probe inputs of the autotuner).
+template <typename T>
+__global__ void fill_kernel(T* __restrict__ p, int64_t n, T v)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
 }
 
 // Misfit partial sums: block b of medium m sums (d - d_obs)^2 over a strided share.

@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -43,6 +44,8 @@ struct Wave {
     std::vector<int> items;    // items resident together, longest schedule first
     int blk0 = 0, nblk = 0;    // their blocks, contiguous in the block table
     std::vector<int> prefix;   // prefix[m]: blocks covering the first m items
+    size_t nblk_off[3] = {0, 0, 0};   // per call mode: active blocks of each launch (persistent form)
+    int n_launch[3] = {0, 0, 0};
     int steps = 0, fwd = 0, adj = 0;
     size_t lam_off = 0, lam_bytes = 0;
 };
@@ -85,6 +88,9 @@ struct fwi_plan {
     void* d_items = nullptr;        // Item<T, Acc>[n_items]
     void* d_media = nullptr;        // MediumDev<T>[n_media]
     unsigned* d_status = nullptr;
+    unsigned* d_bar = nullptr;      // grid barrier words of the persistent form
+    int pgrid = 0;                  // co-resident workgroups of the persistent kernel
+    unsigned spin_limit = 0;
     void* h_stage = nullptr;        // pinned staging for items + media descriptors
     size_t item_bytes = 0, media_bytes = 0;
     hipEvent_t stage_ev = nullptr;
@@ -255,6 +261,77 @@ hipError_t allow_lds_plan(const fwi_plan* p)
     return pick(float(), float());
 }
 
+// ---------------------------------------------------------------- persistent form
+
+template <typename T, typename Acc, int G, int R>
+void* persistent_fn()
+{
+    return reinterpret_cast<void*>(&persistent_kernel<T, G, Acc, R>);
+}
+
+// The persistent kernel of a plan, and its dynamic LDS (none without two-step tiles).
+void* persistent_kernel_of(const fwi_plan* p, size_t* lds)
+{
+    auto pick = [&](auto t, auto a) -> void* {
+        using T = decltype(t);
+        using A = decltype(a);
+        const int R = p->S == 2 ? p->rows : 1;
+        *lds = 0;
+        auto byG = [&](auto g) -> void* {
+            constexpr int G = decltype(g)::value;
+            if (R == 2) { if (p->S == 2) *lds = Lds2<T, G, 2, true>::bytes; return persistent_fn<T, A, G, 2>(); }
+            if (R == 4) { if (p->S == 2) *lds = Lds2<T, G, 4, true>::bytes; return persistent_fn<T, A, G, 4>(); }
+            if (p->S == 2) *lds = Lds2<T, G, 1, true>::bytes;
+            return persistent_fn<T, A, G, 1>();
+        };
+        if (p->G == 1) return byG(std::integral_constant<int, 1>());
+        if (p->G == 2) return byG(std::integral_constant<int, 2>());
+        return byG(std::integral_constant<int, 4>());
+    };
+    if (p->dtype == FWI_F64) return pick(double(), double());
+    if (p->acc_double) return pick(float(), double());
+    return pick(float(), float());
+}
+
+// Workgroups of the persistent kernel that are co-resident, a multiple of the XCD count.
+hipError_t persistent_grid(fwi_plan* p, int* grid)
+{
+    size_t lds = 0;
+    const void* fn = persistent_kernel_of(p, &lds);
+    if (lds > 0) {
+        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    int per_cu = 0, dev = 0, cus = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kBlock, lds);
+    if (e != hipSuccess) return e;
+    if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+    if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
+    const int cap = per_cu * cus / kXcd * kXcd;
+    *grid = std::max(kXcd, cap);
+    return hipSuccess;
+}
+
+void launch_persistent(fwi_plan* p, hipStream_t st, const Wave& w, int mode_idx, int mode)
+{
+    size_t lds = 0;
+    void* fn = persistent_kernel_of(p, &lds);
+    int max_nb = 0;
+    for (int nb : w.prefix) max_nb = std::max(max_nb, nb);
+    const int grid = std::max(kXcd, std::min(p->pgrid, (max_nb + kXcd - 1) / kXcd * kXcd));
+    auto* tabs = reinterpret_cast<unsigned char*>(p->d_tables);
+    const void* items = p->d_items;
+    const int2* blocks = p->d_blocks + w.blk0;
+    const int* nblk = reinterpret_cast<const int*>(tabs + w.nblk_off[mode_idx]);
+    int n_launch = w.n_launch[mode_idx];
+    int rows = p->rows;
+    unsigned* bar = p->d_bar;
+    unsigned spin = p->spin_limit;
+    unsigned* status = p->d_status;
+    void* args[] = {&items, &blocks, &nblk, &n_launch, &mode, &rows, &bar, &spin, &status};
+    (void)hipLaunchKernel(fn, dim3(grid), dim3(kTileX, kWavesZ), args, lds, st);
+}
+
 // Launch kinds present in a wave at launch s of a call: bit k set when some
 // item needs kind k (host mirror of the device schedule).
 unsigned wave_kinds(const fwi_plan* p, const Wave& w, int s, int mode, int* n_active)
@@ -352,6 +429,9 @@ static fwi_status create_impl(fwi_plan* p, fwi_dtype dtype, const fwi_grid* grid
     if (o.mem_budget < 0) return fail(p, FWI_ERR_INVALID, "mem_budget must be >= 0");
     if (o.use_graph && o.mode != FWI_BATCHED) return fail(p, FWI_ERR_INVALID, "use_graph requires FWI_BATCHED");
     if (o.forward_only != 0 && o.forward_only != 1) return fail(p, FWI_ERR_INVALID, "forward_only must be 0 or 1");
+    if (o.persistent != 0 && o.persistent != 1) return fail(p, FWI_ERR_INVALID, "persistent must be 0 or 1");
+    if (o.persistent && o.mode != FWI_BATCHED) return fail(p, FWI_ERR_INVALID, "persistent requires FWI_BATCHED");
+    if (o.barrier_spin < 0) return fail(p, FWI_ERR_INVALID, "barrier_spin must be >= 0");
     for (int i = 0; i < n_media; ++i) {
         std::string msg;
         fwi_status st = validate_grid(grids[i], i, msg);
@@ -361,17 +441,26 @@ static fwi_status create_impl(fwi_plan* p, fwi_dtype dtype, const fwi_grid* grid
     p->dtype = dtype;
     p->opt = o;
     p->G = o.group ? o.group : (o.mode == FWI_PLAIN ? 1 : 4);
-    // default: two steps per launch on 64 x 8 tiles (one step on 64 x 16 for the plain form)
-    p->S = o.steps_per_launch ? o.steps_per_launch : (o.mode == FWI_PLAIN ? 1 : 2);
-    p->rows = o.rows ? o.rows : (p->S == 2 ? 2 : 4);
-    if (p->S == 2 && p->rows != 1 && p->rows != 2 && p->rows != 4)
-        return fail(p, FWI_ERR_INVALID, "two steps per launch need rows of 1, 2 or 4");
-    if (p->S == 2) {
+    // default: two steps per launch on 64 x 8 tiles (one step on 64 x 16 for the plain
+    // form); with an explicit rows value that two-step tiles do not support, one step
+    auto two_step_ok = [&](int rows) {
+        if (rows != 1 && rows != 2 && rows != 4) return false;
         // LDS of the two-step adjoint: tile + 2 (fields, q, bt) and three tile + 1 field planes
-        const size_t n0 = (size_t)(kTileX + 4) * (kWavesZ * p->rows + 4), n1 = (size_t)(kTileX + 2) * (kWavesZ * p->rows + 2);
+        const size_t n0 = (size_t)(kTileX + 4) * (kWavesZ * rows + 4), n1 = (size_t)(kTileX + 2) * (kWavesZ * rows + 2);
         const size_t ts = dtype == FWI_F64 ? 8 : 4;
-        if ((n0 * (p->G + 2) + 3 * n1 * p->G) * ts > kLdsBytes)
-            return fail(p, FWI_ERR_INVALID, "two-step tile does not fit the 160 KiB of LDS: use fewer rows");
+        return (n0 * (p->G + 2) + 3 * n1 * p->G) * ts <= kLdsBytes;
+    };
+    if (o.steps_per_launch == 2) {
+        p->S = 2;
+        p->rows = o.rows ? o.rows : 2;
+        if (!two_step_ok(p->rows))
+            return fail(p, FWI_ERR_INVALID, "two steps per launch need rows of 1, 2 or 4 whose tile fits the LDS");
+    } else if (o.steps_per_launch == 1 || o.mode == FWI_PLAIN) {
+        p->S = 1;
+        p->rows = o.rows ? o.rows : 4;
+    } else {
+        p->rows = o.rows ? o.rows : 2;
+        p->S = two_step_ok(p->rows) ? 2 : 1;
     }
     p->acc_double = dtype == FWI_F64 || o.acc_double;
     p->tsize = dtype == FWI_F64 ? 8 : 4;
@@ -683,13 +772,29 @@ static fwi_status create_impl(fwi_plan* p, fwi_dtype dtype, const fwi_grid* grid
         w.nblk = (int)p->blocks.size() - w.blk0;
     }
     const size_t blocks_off = tab_put(p->blocks.data(), p->blocks.size() * sizeof(int2));
+    // persistent form: active-block count of every launch of every wave and call mode
+    for (auto& w : p->waves) {
+        const int counts[3] = {w.steps, w.fwd, w.adj};
+        const int modes[3] = {kRunAll, kRunFwdOnly, kRunAdjOnly};
+        for (int m = 0; m < 3; ++m) {
+            std::vector<int32_t> nb(std::max(1, counts[m]), 0);
+            for (int s2 = 0; s2 < counts[m]; ++s2) {
+                int n_active = 0;
+                (void)wave_kinds(p, w, s2, modes[m], &n_active);
+                nb[s2] = w.prefix[n_active];
+            }
+            w.nblk_off[m] = tab_put(nb.data(), nb.size() * 4);
+            w.n_launch[m] = counts[m];
+        }
+    }
     p->item_bytes = (p->dtype == FWI_F64 ? sizeof(Item<double, double>)
                      : p->acc_double ? sizeof(Item<float, double>) : sizeof(Item<float, float>)) * p->items.size();
     p->media_bytes = (p->dtype == FWI_F64 ? sizeof(MediumDev<double>) : sizeof(MediumDev<float>)) * p->media.size();
     const size_t items_off = align_up(tab.size());
     const size_t media_off = align_up(items_off + p->item_bytes);
     const size_t status_off = align_up(media_off + p->media_bytes);
-    p->tables_bytes = status_off + kAlign;
+    const size_t bar_off = status_off + kAlign;
+    p->tables_bytes = bar_off + kAlign;
     tab.resize(p->tables_bytes, 0);
 
     HIPCHK(p, hipMalloc(&p->d_tables, p->tables_bytes));
@@ -699,6 +804,9 @@ static fwi_status create_impl(fwi_plan* p, fwi_dtype dtype, const fwi_grid* grid
     p->d_items = base + items_off;
     p->d_media = base + media_off;
     p->d_status = reinterpret_cast<unsigned*>(base + status_off);
+    p->d_bar = reinterpret_cast<unsigned*>(base + bar_off);
+    p->spin_limit = o.barrier_spin > 0 ? (unsigned)o.barrier_spin : (1u << 21);
+    if (o.persistent) HIPCHK(p, persistent_grid(p, &p->pgrid));
     HIPCHK(p, hipHostMalloc(&p->h_stage, align_up(p->item_bytes) + align_up(p->media_bytes), hipHostMallocDefault));
     HIPCHK(p, allow_lds_plan(p));
     HIPCHK(p, hipEventCreateWithFlags(&p->stage_ev, hipEventDisableTiming));
@@ -876,6 +984,11 @@ void enqueue_sequence(fwi_plan* p, hipStream_t st, unsigned char* ws, int call, 
     for (const Wave& w : p->waves) {
         const int S = call == kExecute ? w.steps : call == kForward ? w.fwd : w.adj;
         if (call != kForward) zero_bytes(st, ws + w.lam_off, w.lam_bytes);
+        if (p->opt.persistent) {
+            hipLaunchKernelGGL(zero_kernel<unsigned>, dim3(1), dim3(64), 0, st, p->d_bar, (int64_t)4);
+            launch_persistent(p, st, w, call == kExecute ? 0 : call == kForward ? 1 : 2, mode);
+            continue;
+        }
         for (int s = 0; s < S; ++s) {
             int n_active = 0;
             const unsigned kinds = wave_kinds(p, w, s, mode, &n_active);
@@ -979,8 +1092,235 @@ extern "C" fwi_status fwi_plan_check(fwi_plan* p)
     HIPCHK(p, hipStreamSynchronize(p->last_stream));
     unsigned flags = 0;
     HIPCHK(p, hipMemcpy(&flags, p->d_status, sizeof flags, hipMemcpyDeviceToHost));
+    // the first cause wins: a bad medium or an abandoned launch also leaves non-finite outputs
     if (flags & kFlagMedium) return fail(p, FWI_ERR_MEDIUM, "c or rho not positive and finite");
     if (flags & kFlagCfl) return fail(p, FWI_ERR_CFL, "a cell's c exceeds the declared c_max");
+    if (flags & kFlagBarrier) return fail(p, FWI_ERR_HIP, "persistent grid barrier abandoned after its spin limit");
     if (flags & kFlagNonfinite) return fail(p, FWI_ERR_NONFINITE, "non-finite misfit or gradient");
+    return FWI_OK;
+}
+
+// ----------------------------------------------------------------------------- autotuner
+//
+// Tile shape and steps per launch are picked by timing short probes of the
+// real kernels on the device: the caller's grids (a spread of up to 12 of
+// them) with their schedules cut to 24 steps, every plane kept, a
+// homogeneous medium at 80% of c_max, zero wavelets and observed traces
+// (the kernels' cost does not depend on the values).  Each feasible
+// candidate runs one warm-up gradient and two timed ones; the fastest per
+// cell-update wins.  Results are cached in a small JSON file keyed by the
+// GPU architecture, dtype, mode, group and the grids' size class.
+
+namespace {
+
+struct TuneChoice {
+    int S = 0, rows = 0;
+    double ns = 0;
+};
+
+std::string tune_key(const char* arch, fwi_dtype dtype, const fwi_options& o, int G, const fwi_grid* grids, int n)
+{
+    double cells = 0;
+    int items = 0;
+    for (int i = 0; i < n; ++i) {
+        cells += (double)grids[i].nx * grids[i].nz;
+        items += (grids[i].n_tx + G - 1) / G;
+    }
+    char buf[256];
+    std::string a(arch);
+    a = a.substr(0, a.find(':'));
+    std::snprintf(buf, sizeof buf, "%s|%s|%s|G%d|c%ld|i%ld", a.c_str(), dtype == FWI_F64 ? "f64" : "f32",
+                  o.mode == FWI_PLAIN ? "plain" : "batched", G, std::lround(std::log2(cells / n)),
+                  std::lround(std::log2((double)items)));
+    return buf;
+}
+
+// Entries are lines  "key": {"steps_per_launch": S, "rows": R, "ns_per_update": X}
+bool cache_read(const char* path, std::vector<std::pair<std::string, TuneChoice>>& ent)
+{
+    FILE* f = std::fopen(path, "r");
+    if (!f) return false;
+    char line[1024];
+    while (std::fgets(line, sizeof line, f)) {
+        const char* q0 = std::strchr(line, '"');
+        if (!q0) continue;
+        const char* q1 = std::strchr(q0 + 1, '"');
+        if (!q1) continue;
+        TuneChoice c;
+        const char* sp = std::strstr(q1, "\"steps_per_launch\":");
+        const char* rw = std::strstr(q1, "\"rows\":");
+        const char* ns = std::strstr(q1, "\"ns_per_update\":");
+        if (!sp || !rw || !ns) continue;
+        c.S = std::atoi(sp + 19);
+        c.rows = std::atoi(rw + 7);
+        c.ns = std::atof(ns + 16);
+        ent.emplace_back(std::string(q0 + 1, q1), c);
+    }
+    std::fclose(f);
+    return true;
+}
+
+void cache_write(const char* path, const std::vector<std::pair<std::string, TuneChoice>>& ent)
+{
+    const std::string tmp = std::string(path) + ".tmp";
+    FILE* f = std::fopen(tmp.c_str(), "w");
+    if (!f) return;
+    std::fprintf(f, "{\n");
+    for (size_t i = 0; i < ent.size(); ++i)
+        std::fprintf(f, "\"%s\": {\"steps_per_launch\": %d, \"rows\": %d, \"ns_per_update\": %.6g}%s\n",
+                     ent[i].first.c_str(), ent[i].second.S, ent[i].second.rows, ent[i].second.ns,
+                     i + 1 < ent.size() ? "," : "");
+    std::fprintf(f, "}\n");
+    std::fclose(f);
+    std::rename(tmp.c_str(), path);
+}
+
+template <typename T>
+void fill(hipStream_t st, void* p, int64_t n, double v)
+{
+    hipLaunchKernelGGL(fill_kernel<T>, dim3(grid_for(n, 256, 4096)), dim3(256), 0, st, reinterpret_cast<T*>(p), n, (T)v);
+}
+
+struct ProbeBuffers {
+    std::vector<void*> ptr;
+    ~ProbeBuffers()
+    {
+        for (void* q : ptr) (void)hipFree(q);
+    }
+    void* get(size_t bytes)
+    {
+        void* q = nullptr;
+        if (hipMalloc(&q, std::max<size_t>(bytes, 256)) != hipSuccess) return nullptr;
+        ptr.push_back(q);
+        return q;
+    }
+};
+
+}  // namespace
+
+extern "C" fwi_status fwi_autotune(fwi_dtype dtype, const fwi_grid* grids, int32_t n_media, const fwi_options* base,
+                                   fwi_options* out, double* ns_per_update)
+{
+    g_create_error.clear();
+    if (!grids || n_media < 1 || !out) { g_create_error = "grids and out must be non-NULL"; return FWI_ERR_INVALID; }
+    if (dtype != FWI_F32 && dtype != FWI_F64) { g_create_error = "unknown dtype"; return FWI_ERR_INVALID; }
+    fwi_options o{};
+    o.mode = FWI_BATCHED;
+    if (base) o = *base;
+    for (int i = 0; i < n_media; ++i) {
+        std::string msg;
+        fwi_status st = validate_grid(grids[i], i, msg);
+        if (st != FWI_OK) { g_create_error = msg; return st; }
+    }
+    const int G = o.group ? o.group : (o.mode == FWI_PLAIN ? 1 : 4);
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+        g_create_error = "no HIP device";
+        return FWI_ERR_HIP;
+    }
+    const std::string key = tune_key(prop.gcnArchName, dtype, o, G, grids, n_media);
+    std::vector<std::pair<std::string, TuneChoice>> cache;
+    if (o.tune_cache && cache_read(o.tune_cache, cache))
+        for (auto& e : cache)
+            if (e.first == key && e.second.S > 0) {
+                *out = o;
+                out->steps_per_launch = e.second.S;
+                out->rows = e.second.rows;
+                if (ns_per_update) *ns_per_update = e.second.ns;
+                return FWI_OK;
+            }
+
+    // probe grids: a spread of up to 12 media with their schedules cut to 24 steps
+    const int n_probe = std::min(n_media, 12);
+    std::vector<fwi_grid> pg(n_probe);
+    for (int i = 0; i < n_probe; ++i) {
+        pg[i] = grids[(int64_t)i * n_media / n_probe];
+        pg[i].nt = std::min(pg[i].nt, 24);
+    }
+    const size_t ts = dtype == FWI_F64 ? 8 : 4;
+    hipStream_t st = nullptr;
+    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+        g_create_error = "hipStreamCreate failed";
+        return FWI_ERR_HIP;
+    }
+    ProbeBuffers buf;
+    std::vector<fwi_io> io(n_probe);
+    bool ok = true;
+    for (int i = 0; i < n_probe && ok; ++i) {
+        const fwi_grid& g = pg[i];
+        const int64_t nc = (int64_t)g.nx * g.nz, ntr = (int64_t)g.n_tx * g.nt * g.n_rcv;
+        fwi_io& d = io[i];
+        std::memset(&d, 0, sizeof d);
+        void *c = buf.get(nc * ts), *rho = buf.get(nc * ts), *w = buf.get((int64_t)g.n_tx * g.nt * ts);
+        void *obs = buf.get(ntr * ts), *tr = buf.get(ntr * ts), *gc = buf.get(nc * ts), *gr = buf.get(nc * ts);
+        void* mf = buf.get(sizeof(double));
+        if (!c || !rho || !w || !obs || !tr || !gc || !gr || !mf) { ok = false; break; }
+        if (dtype == FWI_F64) {
+            fill<double>(st, c, nc, 0.8 * g.c_max); fill<double>(st, rho, nc, 1000.0);
+            fill<double>(st, w, (int64_t)g.n_tx * g.nt, 0.0); fill<double>(st, obs, ntr, 0.0);
+        } else {
+            fill<float>(st, c, nc, 0.8 * g.c_max); fill<float>(st, rho, nc, 1000.0);
+            fill<float>(st, w, (int64_t)g.n_tx * g.nt, 0.0); fill<float>(st, obs, ntr, 0.0);
+        }
+        d.c = c; d.rho = rho; d.wavelet = w; d.d_obs = obs; d.traces = tr; d.grad_c = gc; d.grad_rho = gr;
+        d.misfit = reinterpret_cast<double*>(mf);
+    }
+    TuneChoice best;
+    if (ok) {
+        const int cands[][2] = {{2, 1}, {2, 2}, {2, 4}, {1, 2}, {1, 4}, {1, 8}};
+        hipEvent_t e0, e1;
+        (void)hipEventCreate(&e0);
+        (void)hipEventCreate(&e1);
+        for (auto& cd : cands) {
+            if (o.mode == FWI_PLAIN && cd[0] == 2) continue;
+            fwi_options po = o;
+            po.steps_per_launch = cd[0];
+            po.rows = cd[1];
+            po.ckpt_interval = 1 << 30;
+            po.use_graph = 0;
+            po.persistent = 0;
+            po.forward_only = 0;
+            po.tune_cache = nullptr;
+            fwi_plan* plan = nullptr;
+            if (fwi_plan_create(&plan, dtype, pg.data(), n_probe, &po) != FWI_OK) continue;
+            if (plan->S != cd[0]) { fwi_plan_destroy(plan); continue; }
+            void* ws = nullptr;
+            if (hipMalloc(&ws, plan->ws_bytes) != hipSuccess) { fwi_plan_destroy(plan); continue; }
+            bool good = fwi_plan_execute(plan, io.data(), ws, plan->ws_bytes, st) == FWI_OK;
+            good = good && hipEventRecord(e0, st) == hipSuccess;
+            for (int r = 0; r < 2 && good; ++r)
+                good = fwi_plan_execute(plan, io.data(), ws, plan->ws_bytes, st) == FWI_OK;
+            good = good && hipEventRecord(e1, st) == hipSuccess && hipEventSynchronize(e1) == hipSuccess;
+            good = good && fwi_plan_check(plan) == FWI_OK;
+            float ms = 0;
+            if (good && hipEventElapsedTime(&ms, e0, e1) == hipSuccess) {
+                const double ns = ms * 1e6 / (2.0 * (double)plan->cell_updates);
+                if (best.S == 0 || ns < best.ns) best = TuneChoice{cd[0], cd[1], ns};
+            }
+            (void)hipStreamSynchronize(st);
+            (void)hipFree(ws);
+            fwi_plan_destroy(plan);
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+    }
+    (void)hipStreamSynchronize(st);
+    (void)hipStreamDestroy(st);
+    if (best.S == 0) {
+        g_create_error = ok ? "no candidate could be timed" : "probe allocation failed";
+        return ok ? FWI_ERR_HIP : FWI_ERR_NOMEM;
+    }
+    if (o.tune_cache) {
+        bool found = false;
+        for (auto& e : cache)
+            if (e.first == key) { e.second = best; found = true; }
+        if (!found) cache.emplace_back(key, best);
+        cache_write(o.tune_cache, cache);
+    }
+    *out = o;
+    out->steps_per_launch = best.S;
+    out->rows = best.rows;
+    if (ns_per_update) *ns_per_update = best.ns;
     return FWI_OK;
 }

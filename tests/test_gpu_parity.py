@@ -224,3 +224,66 @@ def test_forward_only_plan(spl):
         assert np.array_equal(a["traces"], b["traces"])
     with pytest.raises(F.FwiError):
         gpu_run(media, obs, dtype="f32", forward_only=True, steps_per_launch=spl)
+
+
+# ---------------------------------------------------------------- persistent form
+
+def _two_media():
+    media = [_seam_medium(38, nt=101, n_tx=5), W.small_random_medium(39, 90, 66, 60, n_tx=2, n_rcv=4, npml=3)]
+    obs = [_observed(m, 50 + i) for i, m in enumerate(media)]
+    return media, obs
+
+
+@pytest.mark.parametrize("spl", [1, 2])
+def test_persistent_matches_launch_per_step(spl):
+    """One launch per wave with device-wide barriers gives bitwise the
+    per-step launches' results (and the oracle's within the FP32 bars)."""
+    media, obs = _two_media()
+    eager, _ = gpu_run(media, obs, dtype="f32", ckpt=7, steps_per_launch=spl)
+    pers, plan = gpu_run(media, obs, dtype="f32", ckpt=7, steps_per_launch=spl, persistent=True)
+    for a, b, m, o in zip(eager, pers, media, obs):
+        for k in ("traces", "grad_c", "grad_rho", "misfit"):
+            assert np.array_equal(a[k], b[k]), k
+        _check(b, oracle_grad(m, o), "f32")
+
+
+def test_persistent_graph_replays():
+    """The persistent launch recorded in a hipGraph: every replay equals the eager result."""
+    media, obs = _two_media()
+    eager, _ = gpu_run(media, obs, dtype="f32", ckpt=7)
+    reps, _ = gpu_run(media, obs, dtype="f32", ckpt=7, persistent=True, use_graph=True, reps=3)
+    for r in reps:
+        for a, b in zip(eager, r):
+            for k in ("traces", "grad_c", "grad_rho", "misfit"):
+                assert np.array_equal(a[k], b[k]), k
+
+
+def test_persistent_barrier_limit_reports_error():
+    """A barrier spin limit of one poll (forced from the host) abandons the
+    launch: every workgroup exits and fwi_plan_check reports FWI_ERR_HIP."""
+    import paper_2603_04070_amd as F
+    media, obs = _two_media()
+    with pytest.raises(F.FwiError) as e:
+        gpu_run(media, obs, dtype="f32", ckpt=7, persistent=True, barrier_spin=1)
+    assert e.value.status == 6 and "barrier" in str(e.value)
+
+
+def test_autotune_choice_and_cache(tmp_path):
+    """The autotuner returns a feasible (steps per launch, rows) pair, writes
+    it to its JSON cache and reuses it; a plan built with it passes parity."""
+    import json
+    import paper_2603_04070_amd as F
+    media, obs = _two_media()
+    grids = [F.GridSpec.of(m.geom, float(m.c.max()) * 1.0001) for m in media]
+    cache = str(tmp_path / "tune.json")
+    a = F.autotune(grids, dtype="f32", cache=cache)
+    assert (a["steps_per_launch"], a["rows"]) in {(2, 1), (2, 2), (2, 4), (1, 2), (1, 4), (1, 8)}
+    assert a["ns_per_update"] > 0
+    entries = json.load(open(cache))
+    assert len(entries) == 1
+    b = F.autotune(grids, dtype="f32", cache=cache)
+    assert (b["steps_per_launch"], b["rows"], b["ns_per_update"]) == (a["steps_per_launch"], a["rows"],
+                                                                     pytest.approx(a["ns_per_update"], rel=1e-5))
+    res, plan = gpu_run(media, obs, dtype="f32", ckpt=7, steps_per_launch=a["steps_per_launch"], rows=a["rows"])
+    for r, m, o in zip(res, media, obs):
+        _check(r, oracle_grad(m, o), "f32")
