@@ -98,8 +98,8 @@ struct fwi_plan {
     hipStream_t last_stream = nullptr;
     bool have_call = false;
 
-    // forward -> adjoint state
-    const void* fwd_ws = nullptr;
+    // workspaces holding a forward's replay state for a later adjoint
+    std::vector<const void*> fwd_ws;
 
     // hipGraph replay of the batched gradient
     hipStream_t cap_stream = nullptr;
@@ -1024,7 +1024,8 @@ fwi_status run_call(fwi_plan* p, const fwi_io* io, void* workspace, size_t bytes
     }
     if (p->opt.forward_only && (want_grad || call == kAdjoint))
         return fail(p, FWI_ERR_INVALID, "forward-only plan: no adjoint or gradient");
-    if (call == kAdjoint && p->fwd_ws != workspace) return fail(p, FWI_ERR_STATE, "no forward state in this workspace");
+    if (call == kAdjoint && std::find(p->fwd_ws.begin(), p->fwd_ws.end(), workspace) == p->fwd_ws.end())
+        return fail(p, FWI_ERR_STATE, "no forward state in this workspace");
     if (call != kExecute && p->waves.size() > 1)
         return fail(p, FWI_ERR_INVALID, "forward/adjoint need every item resident at once: use FWI_BATCHED "
                                         "with a memory budget that holds all items");
@@ -1064,7 +1065,9 @@ fwi_status run_call(fwi_plan* p, const fwi_io* io, void* workspace, size_t bytes
     HIPCHK(p, hipGetLastError());
     p->last_stream = st;
     p->have_call = true;
-    p->fwd_ws = (call == kForward || (call == kExecute && !want_grad)) ? workspace : nullptr;
+    // a forward leaves replay state in its workspace; any other call consumes or overwrites it
+    p->fwd_ws.erase(std::remove(p->fwd_ws.begin(), p->fwd_ws.end(), workspace), p->fwd_ws.end());
+    if (call == kForward || (call == kExecute && !want_grad)) p->fwd_ws.push_back(workspace);
     return FWI_OK;
 }
 
