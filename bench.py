@@ -33,7 +33,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="uneven64", choices=["uneven64", "rodgauss512", "disc128"])
+    ap.add_argument("--workload", default="uneven64", choices=["uneven64", "rodgauss512", "disc128", "unfold16"])
+    ap.add_argument("--unfold-k", type=int, default=8, help="unfolded iterations (unfold16)")
+    ap.add_argument("--unfold-backprop", default="fd", choices=["none", "fd"])
     ap.add_argument("--media", type=int, default=64, help="media of the uneven workload")
     ap.add_argument("--nt", type=int, default=0, help="override every medium's step count (counter runs)")
     ap.add_argument("--mode", default="batched", choices=["batched", "plain"])
@@ -136,8 +138,69 @@ def time_gradient(plan, media_dev, d_obs, dtype, steps, warmup, dev):
     return ms, ios
 
 
+def run_unfold(args):
+    """16 media 512^2, K unfolded iterations of (gradient over 32 transmits,
+    4000 steps, FP32) + a random-init 3-layer 3x3 CNN update, forward and
+    backward of an MSE loss on C_K."""
+    import numpy as np
+    import torch
+    import workloads as W
+    import paper_2603_04070_amd as F
+    from paper_2603_04070_amd.unfold import DUFWI
+    dev = torch.device("cuda:0")
+    media = [W.c2_medium(5000 + i, n_tx=32) for i in range(16)]
+    partners = [W.partner_medium(m, 6000 + i) for i, m in enumerate(media)]
+    if args.nt > 0:
+        for m in media + partners:
+            m.geom.nt = args.nt
+            m.wavelet = m.wavelet[:, :args.nt]
+    c_max = 1700.0
+    d_obs = observed(partners, "f32", args, c_max, dev)
+    grids = [F.GridSpec.of(m.geom, c_max) for m in media]
+    torch.manual_seed(0)
+    model = DUFWI(grids, K=args.unfold_k, arch="small", hidden=32, physics_backprop=args.unfold_backprop).to(dev)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float32)).to(dev)
+    c0 = torch.full((16, 512, 512), 1540.0, device=dev)
+    rho = torch.stack([t(m.rho) for m in media])
+    wav = [t(m.wavelet) for m in media]
+    target = torch.stack([t(m.c) for m in media])
+    upd = sum(g.n_tx * g.nx * g.nz * g.nt * 2 for g in grids)
+    times = []
+    for it in range(args.warmup + args.steps):
+        c_in = c0.clone().requires_grad_(args.unfold_backprop == "fd")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        cK = model(c_in, rho, wav, d_obs)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        loss = ((cK - target) ** 2).mean()
+        loss.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        if it >= args.warmup:
+            times.append((t1 - t0, t2 - t1))
+    fw = float(np.mean([a for a, _ in times]))
+    bw = float(np.mean([b for _, b in times]))
+    grads_fw = args.unfold_k
+    grads_bw = 2 * args.unfold_k if args.unfold_backprop == "fd" else 0
+    line = {
+        "metric": "DUFWI unfolded forward+backward time", "value": round(fw + bw, 3), "unit": "s",
+        "higher_is_better": False, "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"unfold16: 16 rod+Gaussian media 512^2, 32 transmits, {grids[0].nt} steps, "
+                               f"K={args.unfold_k}, 3-layer 3x3 CNN, physics backprop {args.unfold_backprop}"},
+        "forward_s": round(fw, 3), "backward_s": round(bw, 3),
+        "gradient_evaluations": grads_fw + grads_bw,
+        "physics_gcell_updates_per_s": round(upd * (grads_fw + grads_bw) / (fw + bw) / 1e9, 2),
+    }
+    print(json.dumps(line))
+
+
 def main():
     args = parse()
+    if args.workload == "unfold16":
+        run_unfold(args)
+        return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build measures the single-GPU hot path "
               "(multi-GPU sharding is described, not run)", file=sys.stderr)
