@@ -23,6 +23,10 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+def progress(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 METRIC = "FWI gradient Gcell-updates/s (fwd+adj), % HBM roofline; batched vs plain"
 HBM_PEAK_GBS = 8000.0          # MI355X published HBM3E bandwidth
 BYTES_PER_UPDATE = 24          # algorithmic bytes per cell-update (48 per forward+adjoint pair)
@@ -226,8 +230,10 @@ def main():
             m.wavelet = m.wavelet[:, :args.nt]
         desc += f" [steps overridden to {args.nt}]"
     c_max = 1.02 * max(float(np.max(m.c)) for m in media + partners)
+    progress(f"workload built: {desc}")
     d_obs = observed(partners, dtype, args, c_max, dev)
     mdev = to_dev(media, dtype, dev)
+    progress("observed traces computed")
 
     tuned = None
     if args.tune and args.rows == 0 and args.spl == 0:
@@ -236,9 +242,12 @@ def main():
         tuned = F.autotune(grids, dtype=dtype, mode=args.mode, group=args.group, cache=args.tune_cache or None)
         tuned["seconds"] = round(time.perf_counter() - t0, 2)
         args.rows, args.spl = tuned["rows"], tuned["steps_per_launch"]
+        progress(f"autotuned: {tuned}")
     plan = make_plan(media, dtype, args.mode, args, c_max)
     info = plan.info
+    progress(f"plan: {info}")
     ms, _ = time_gradient(plan, mdev, d_obs, dtype, args.steps, args.warmup, dev)
+    progress(f"timed: {ms:.1f} ms per gradient")
     updates = info["cell_updates"]
     value = updates / (ms * 1e-3) / 1e9
     launches = max(1, info["launches"])
@@ -261,6 +270,7 @@ def main():
         bms, _ = time_gradient(bp, sub_dev, sub_obs, dtype, 1, 1, dev)
         del bp
         torch.cuda.empty_cache()
+        progress("plain form timed")
         plain = {"value": pu / (pms * 1e-3) / 1e9, "unit": "Gcell-updates/s", "media": k,
                  "batched_same_media": pu / (bms * 1e-3) / 1e9,
                  "speedup_batched_over_plain": pms / bms,
@@ -269,8 +279,9 @@ def main():
     cpu = None
     if args.cpu_baseline:
         cpu = run_cpu_baseline(media, args)
+        progress("oracle baseline timed")
 
-    traffic = load_traffic()
+    traffic = load_traffic(info, launches)
     line = {
         "metric": METRIC,
         "value": round(value, 3),
@@ -303,7 +314,7 @@ def main():
         "hbm_roofline_pct": round(100.0 * value * 1e9 * BYTES_PER_UPDATE / (HBM_PEAK_GBS * 1e9), 2),
         "roofline": {
             "bound": "hbm",
-            "kernel": "step_kernel",
+            "kernel": "step kernels (fwd2_kernel, adj2_kernel, fwd1_kernel, adj1_kernel): 24 B per update each",
             "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
@@ -346,9 +357,11 @@ def run_cpu_baseline(media, args):
             "sample": f"medium 0 ({g.nx}x{g.nz}), {ntx} transmits, first {steps} steps, FP64, d_obs = 0"}
 
 
-def load_traffic():
-    """HBM bytes per launch from the committed rocprofv3 counter runs, if they
-    were taken on the current kernel source (else null)."""
+def load_traffic(info, launches):
+    """HBM bytes per step-kernel launch: the bytes per executed cell-update
+    measured by the committed rocprofv3 counter runs (FETCH_SIZE, WRITE_SIZE,
+    scaled by a 1 GiB copy) times this workload's executed updates per
+    launch; null when the kernel source differs from the one measured."""
     path = os.path.join(ROOT, "profiles", "step_kernel_traffic.json")
     if not os.path.exists(path):
         return None
@@ -356,7 +369,8 @@ def load_traffic():
     src = open(os.path.join(ROOT, "paper_2603_04070_amd", "csrc", "fwi_kernels.hpp"), "rb").read()
     if rec.get("kernel_source_sha256") != hashlib.sha256(src).hexdigest():
         return None
-    return rec.get("hbm_bytes_per_launch")
+    executed = info["cell_updates"] + info["recompute_updates"]
+    return int(rec["bytes_per_executed_update"] * executed / launches)
 
 
 if __name__ == "__main__":

@@ -125,7 +125,7 @@ typedef struct fwi_plan_info {
     int32_t n_items;         /* work items (medium, transmit group)                             */
     int32_t group;           /* transmits per item                                              */
     int32_t rows;            /* rows per thread                                                 */
-    int32_t launches;        /* step-kernel launches per gradient                               */
+    int32_t launches;        /* step-kernel launches per gradient (1 per wave when persistent)   */
     int32_t max_ckpt;        /* largest K over items (nt when every plane is kept)              */
     int32_t min_ckpt;
     int32_t waves;           /* groups of items run one after another to fit the memory budget */

@@ -73,6 +73,7 @@ struct fwi_plan {
     std::vector<int2> blocks;
     std::vector<Wave> waves;
     int64_t cell_updates = 0, recompute_updates = 0;
+    int64_t kernel_launches = 0;    // step-kernel launches of one gradient
 
     // workspace layout
     size_t ws_bytes = 0;
@@ -513,6 +514,8 @@ static fwi_status create_impl(fwi_plan* p, fwi_dtype dtype, const fwi_grid* grid
     auto auto_k = [&](int T) {
         if (T <= 2) return T;
         int K = (int)std::lround(std::sqrt(2.0 * T));
+        // an even K lets two-step launches tile every segment exactly
+        if (p->S == 2 && K % 2) ++K;
         return std::max(2, std::min(K, T));
     };
     for (auto& it : p->items) {
@@ -772,6 +775,14 @@ static fwi_status create_impl(fwi_plan* p, fwi_dtype dtype, const fwi_grid* grid
         w.nblk = (int)p->blocks.size() - w.blk0;
     }
     const size_t blocks_off = tab_put(p->blocks.data(), p->blocks.size() * sizeof(int2));
+    // step-kernel launches of one gradient (per-step form), or one per wave (persistent)
+    for (auto& w : p->waves) {
+        if (o.persistent) { ++p->kernel_launches; continue; }
+        for (int s2 = 0; s2 < w.steps; ++s2) {
+            int n_active = 0;
+            p->kernel_launches += __builtin_popcount(wave_kinds(p, w, s2, kRunAll, &n_active));
+        }
+    }
     // persistent form: active-block count of every launch of every wave and call mode
     for (auto& w : p->waves) {
         const int counts[3] = {w.steps, w.fwd, w.adj};
@@ -859,9 +870,7 @@ extern "C" fwi_status fwi_plan_get_info(const fwi_plan* p, fwi_plan_info* info)
     info->n_items = (int32_t)p->items.size();
     info->group = p->G;
     info->rows = p->rows;
-    int64_t l = 0;
-    for (auto& w : p->waves) l += w.steps;
-    info->launches = (int32_t)std::min<int64_t>(l, INT32_MAX);
+    info->launches = (int32_t)std::min<int64_t>(p->kernel_launches, INT32_MAX);
     info->waves = (int32_t)p->waves.size();
     info->steps_per_launch = p->S;
     info->max_ckpt = 0;
