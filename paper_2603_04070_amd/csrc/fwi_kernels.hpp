@@ -85,16 +85,61 @@ struct alignas(sizeof(T) * G) Vec {
     T v[G];
 };
 
+// Every buffer the kernels touch outside LDS is device global memory.  The
+// pointers reach the kernels inside work-item descriptors, where the compiler
+// cannot see their address space; without the cast it emits flat loads, which
+// also count against the LDS wait counter, so that every LDS wait in the
+// compute phase would wait for outstanding global loads as well.
+template <typename T>
+__device__ __forceinline__ T ldg(const T* p, int64_t i)
+{
+    return ((const T __attribute__((address_space(1)))*)p)[i];
+}
+
+template <typename T>
+__device__ __forceinline__ void stg(T* p, int64_t i, T v)
+{
+    ((T __attribute__((address_space(1)))*)p)[i] = v;
+}
+
+// The G values of a cell move as one native vector (one 16-byte access for
+// four floats).
+template <typename T, int G>
+struct Native {
+    typedef T type __attribute__((ext_vector_type(G)));
+};
+template <typename T>
+struct Native<T, 1> {
+    typedef T type;
+};
+
 template <typename T, int G>
 __device__ __forceinline__ Vec<T, G> vload(const T* p, int64_t cell)
 {
-    return *reinterpret_cast<const Vec<T, G>*>(p + cell * G);
+    using N = typename Native<T, G>::type;
+    const N n = *(const N __attribute__((address_space(1)))*)(p + cell * G);
+    Vec<T, G> r;
+    if constexpr (G == 1) {
+        r.v[0] = n;
+    } else {
+#pragma unroll
+        for (int g = 0; g < G; ++g) r.v[g] = n[g];
+    }
+    return r;
 }
 
 template <typename T, int G>
 __device__ __forceinline__ void vstore(T* p, int64_t cell, const Vec<T, G>& v)
 {
-    *reinterpret_cast<Vec<T, G>*>(p + cell * G) = v;
+    using N = typename Native<T, G>::type;
+    N n;
+    if constexpr (G == 1) {
+        n = v.v[0];
+    } else {
+#pragma unroll
+        for (int g = 0; g < G; ++g) n[g] = v.v[g];
+    }
+    *(N __attribute__((address_space(1)))*)(p + cell * G) = n;
 }
 
 template <typename T, int G>
@@ -103,6 +148,15 @@ __device__ __forceinline__ Vec<T, G> vzero()
     Vec<T, G> r;
 #pragma unroll
     for (int g = 0; g < G; ++g) r.v[g] = T(0);
+    return r;
+}
+
+template <typename T, int G>
+__device__ __forceinline__ Vec<T, G> vkeep(bool keep, const Vec<T, G>& v)
+{
+    Vec<T, G> r;
+#pragma unroll
+    for (int g = 0; g < G; ++g) r.v[g] = keep ? v.v[g] : T(0);
     return r;
 }
 
@@ -247,6 +301,23 @@ __device__ __forceinline__ T* ckpt_plane(const Item<T, Acc>& it, const Step& st,
     return nullptr;
 }
 
+__device__ __forceinline__ Entry ld_entry(const Entry* p, int i)
+{
+    typedef int32_t I4 __attribute__((ext_vector_type(4)));
+    const I4 v = ((const I4 __attribute__((address_space(1)))*)p)[i];
+    return Entry{v[0], v[1], v[2], v[3]};
+}
+
+// Receiver entries [e0, e1) of one tile.
+struct Span {
+    int e0, e1;
+};
+
+__device__ __forceinline__ Span span_of(const int32_t* off, int tile)
+{
+    return Span{ldg(off, tile), ldg(off, tile + 1)};
+}
+
 template <typename T, int G>
 struct Src {
     int cell[G];
@@ -259,8 +330,8 @@ __device__ __forceinline__ Src<T, G> sources(const Item<T, Acc>& it, int n)
     Src<T, G> s;
 #pragma unroll
     for (int g = 0; g < G; ++g) {
-        s.cell[g] = it.src[g];
-        s.w[g] = s.cell[g] >= 0 ? it.wavelet[(int64_t)(it.tx0 + g) * it.wavelet_stride + n] : T(0);
+        s.cell[g] = ldg(it.src, g);
+        s.w[g] = s.cell[g] >= 0 ? ldg(it.wavelet, (int64_t)(it.tx0 + g) * it.wavelet_stride + n) : T(0);
     }
     return s;
 }
@@ -268,16 +339,15 @@ __device__ __forceinline__ Src<T, G> sources(const Item<T, Acc>& it, int n)
 // Traces d[n] (and d[n+1] from out2) at the receivers of one tile, read back
 // after the whole workgroup has stored its cells.
 template <typename T, typename Acc>
-__device__ __forceinline__ void sample_tile(const Item<T, Acc>& it, int tile, int n, const T* out, const T* out2)
+__device__ __forceinline__ void sample_tile(const Item<T, Acc>& it, Span sp, int n, const T* out, const T* out2)
 {
-    const int e0 = it.tile_off[tile], e1 = it.tile_off[tile + 1];
-    if (e1 <= e0) return;
+    if (sp.e1 <= sp.e0) return;
     __syncthreads();
     const int tid = threadIdx.y * kTileX + threadIdx.x;
-    for (int e = e0 + tid; e < e1; e += kBlock) {
-        const Entry en = it.entries[e];
-        it.traces[en.trace_off + (int64_t)n * it.n_rcv] = out[en.slot];
-        if (out2) it.traces[en.trace_off + (int64_t)(n + 1) * it.n_rcv] = out2[en.slot];
+    for (int e = sp.e0 + tid; e < sp.e1; e += kBlock) {
+        const Entry en = ld_entry(it.entries, e);
+        stg(it.traces, en.trace_off + (int64_t)n * it.n_rcv, ldg(out, en.slot));
+        if (out2) stg(it.traces, en.trace_off + (int64_t)(n + 1) * it.n_rcv, ldg(out2, en.slot));
     }
 }
 
@@ -286,7 +356,7 @@ template <typename T, typename Acc>
 __device__ __forceinline__ T adj_source(const Item<T, Acc>& it, const Entry& en, int m)
 {
     const int64_t o = en.trace_off + (int64_t)m * it.n_rcv;
-    return it.inject_adj ? it.d_adj[o] : T(2) * (it.traces[o] - it.d_obs[o]);
+    return it.inject_adj ? ldg(it.d_adj, o) : T(2) * (ldg(it.traces, o) - ldg(it.d_obs, o));
 }
 
 template <typename T, typename Acc>
@@ -298,18 +368,17 @@ __device__ __forceinline__ bool has_adj_source(const Item<T, Acc>& it)
 // Add the adjoint source of sample m to field plane ``f`` at the receivers of
 // one tile (one thread per run of equal slots, entries of a run in order).
 template <typename T, typename Acc>
-__device__ __forceinline__ void inject_tile(const Item<T, Acc>& it, int tile, int m, T* f)
+__device__ __forceinline__ void inject_tile(const Item<T, Acc>& it, Span sp, int m, T* f)
 {
-    const int e0 = it.tile_off[tile], e1 = it.tile_off[tile + 1];
-    if (e1 <= e0 || m < 0 || !has_adj_source(it)) return;
+    if (sp.e1 <= sp.e0 || m < 0 || !has_adj_source(it)) return;
     __syncthreads();
     const int tid = threadIdx.y * kTileX + threadIdx.x;
-    for (int e = e0 + tid; e < e1; e += kBlock) {
-        const Entry en = it.entries[e];
+    for (int e = sp.e0 + tid; e < sp.e1; e += kBlock) {
+        const Entry en = ld_entry(it.entries, e);
         if (en.run == 0) continue;
         T s = T(0);
-        for (int k = 0; k < en.run; ++k) s += adj_source(it, it.entries[e + k], m);
-        f[en.slot] += s;
+        for (int k = 0; k < en.run; ++k) s += adj_source(it, ld_entry(it.entries, e + k), m);
+        stg(f, en.slot, ldg(f, en.slot) + s);
     }
 }
 
@@ -334,28 +403,28 @@ __device__ void tile_forward(const Item<T, Acc>& it, const Step& st, int tile_x,
     const int ix = tile_x * kTileX + (int)threadIdx.x;
     const int z0 = tile_z * kWavesZ * rows + (int)threadIdx.y * rows;
     if (ix < nx && z0 < nz) {
-        const T ex = it.ex[ix];
+        const T ex = ldg(it.ex, ix);
         const T* cf = it.coef;
         int iz = z0;
         int64_t x = (int64_t)iz * nx + ix;
         Vec<T, G> un = iz > 0 ? vload<T, G>(cur, x - nx) : vzero<T, G>();
         Vec<T, G> uc = vload<T, G>(cur, x);
-        T bn = iz > 0 ? cf[2 * (x - nx) + 1] : T(0);
-        T q = cf[2 * x], bc = cf[2 * x + 1];
+        T bn = iz > 0 ? ldg(cf, 2 * (x - nx) + 1) : T(0);
+        T q = ldg(cf, 2 * x), bc = ldg(cf, 2 * x + 1);
         const int zend = min(z0 + rows, nz);
         for (; iz < zend; ++iz, x += nx) {
             const bool hs = iz < nz - 1, hw = ix > 0, he = ix < nx - 1;
             const Vec<T, G> us = hs ? vload<T, G>(cur, x + nx) : vzero<T, G>();
-            const T qs = hs ? cf[2 * (x + nx)] : T(0);
-            const T bs = hs ? cf[2 * (x + nx) + 1] : T(0);
+            const T qs = hs ? ldg(cf, 2 * (x + nx)) : T(0);
+            const T bs = hs ? ldg(cf, 2 * (x + nx) + 1) : T(0);
             const Vec<T, G> uw = hw ? vload<T, G>(cur, x - 1) : vzero<T, G>();
             const Vec<T, G> ue = he ? vload<T, G>(cur, x + 1) : vzero<T, G>();
-            const T bw = hw ? cf[2 * (x - 1) + 1] : T(0);
-            const T be = he ? cf[2 * (x + 1) + 1] : T(0);
+            const T bw = hw ? ldg(cf, 2 * (x - 1) + 1) : T(0);
+            const T be = he ? ldg(cf, 2 * (x + 1) + 1) : T(0);
             T fw, fe, fn, fs;
             faces<T>(hw, he, iz > 0, hs, bc, bw, be, bn, bs, fw, fe, fn, fs);
             T a, b;
-            damp_coeffs<T>(ex + it.ez[iz], a, b);
+            damp_coeffs<T>(ex + ldg(it.ez, iz), a, b);
             const Vec<T, G> up = vload<T, G>(prev, x);
             Vec<T, G> r;
 #pragma unroll
@@ -370,7 +439,7 @@ __device__ void tile_forward(const Item<T, Acc>& it, const Step& st, int tile_x,
             bn = bc; bc = bs; q = qs;
         }
     }
-    if (sample) sample_tile(it, tile_z * it.tiles_x + tile_x, n, out, (const T*)nullptr);
+    if (sample) sample_tile(it, span_of(it.tile_off, tile_z * it.tiles_x + tile_x), n, out, (const T*)nullptr);
 }
 
 // Adjoint step at time t on one tile, with the imaging of lam^t and u^{t-1}.
@@ -389,7 +458,7 @@ __device__ void tile_adjoint(const Item<T, Acc>& it, const Step& st, int tile_x,
     const int ix = tile_x * kTileX + (int)threadIdx.x;
     const int z0 = tile_z * kWavesZ * rows + (int)threadIdx.y * rows;
     if (ix < nx && z0 < nz) {
-        const T ex = it.ex[ix];
+        const T ex = ldg(it.ex, ix);
         const T* cf = it.coef;
         const bool hw = ix > 0, he = ix < nx - 1;
         const T hf = T(0.5);
@@ -400,29 +469,29 @@ __device__ void tile_adjoint(const Item<T, Acc>& it, const Step& st, int tile_x,
         Vec<T, G> lc = vload<T, G>(cur, x);
         Vec<T, G> uN = iz > 0 ? vload<T, G>(um, x - nx) : vzero<T, G>();
         Vec<T, G> uC = vload<T, G>(um, x);
-        T qn = iz > 0 ? cf[2 * (x - nx)] : T(0);
-        T bn = iz > 0 ? cf[2 * (x - nx) + 1] : T(0);
-        T qc = cf[2 * x], bc = cf[2 * x + 1];
+        T qn = iz > 0 ? ldg(cf, 2 * (x - nx)) : T(0);
+        T bn = iz > 0 ? ldg(cf, 2 * (x - nx) + 1) : T(0);
+        T qc = ldg(cf, 2 * x), bc = ldg(cf, 2 * x + 1);
         const int zend = min(z0 + rows, nz);
         for (; iz < zend; ++iz, x += nx) {
             const bool hs = iz < nz - 1, hn = iz > 0;
             const Vec<T, G> ls = hs ? vload<T, G>(cur, x + nx) : vzero<T, G>();
             const Vec<T, G> uS = hs ? vload<T, G>(um, x + nx) : vzero<T, G>();
-            const T qs = hs ? cf[2 * (x + nx)] : T(0);
-            const T bs = hs ? cf[2 * (x + nx) + 1] : T(0);
+            const T qs = hs ? ldg(cf, 2 * (x + nx)) : T(0);
+            const T bs = hs ? ldg(cf, 2 * (x + nx) + 1) : T(0);
             const Vec<T, G> lw = hw ? vload<T, G>(cur, x - 1) : vzero<T, G>();
             const Vec<T, G> le = he ? vload<T, G>(cur, x + 1) : vzero<T, G>();
             const Vec<T, G> uW = hw ? vload<T, G>(um, x - 1) : vzero<T, G>();
             const Vec<T, G> uE = he ? vload<T, G>(um, x + 1) : vzero<T, G>();
-            const T qw = hw ? cf[2 * (x - 1)] : T(0);
-            const T bw = hw ? cf[2 * (x - 1) + 1] : T(0);
-            const T qe = he ? cf[2 * (x + 1)] : T(0);
-            const T be = he ? cf[2 * (x + 1) + 1] : T(0);
+            const T qw = hw ? ldg(cf, 2 * (x - 1)) : T(0);
+            const T bw = hw ? ldg(cf, 2 * (x - 1) + 1) : T(0);
+            const T qe = he ? ldg(cf, 2 * (x + 1)) : T(0);
+            const T be = he ? ldg(cf, 2 * (x + 1) + 1) : T(0);
             T fw, fe, fn, fs;
             faces<T>(hw, he, hn, hs, bc, bw, be, bn, bs, fw, fe, fn, fs);
             const T cn = hn ? hf : T(1), cs = hs ? hf : T(1);
             T a, b;
-            damp_coeffs<T>(ex + it.ez[iz], a, b);
+            damp_coeffs<T>(ex + ldg(it.ez, iz), a, b);
             const Vec<T, G> lp = vload<T, G>(p1, x);
             Vec<T, G> r;
             Acc sk = Acc(0), sb = Acc(0);
@@ -438,14 +507,14 @@ __device__ void tile_adjoint(const Item<T, Acc>& it, const Step& st, int tile_x,
                 sb += Acc(b1);
             }
             vstore<T, G>(out, x, r);
-            accK[x] += sk;
-            accB[x] += sb;
+            stg(accK, x, ldg(accK, x) + sk);
+            stg(accB, x, ldg(accB, x) + sb);
             ln = lc; lc = ls; uN = uC; uC = uS;
             qn = qc; qc = qs; bn = bc; bc = bs;
         }
     }
     // adjoint source of lam^{t-1}: sample t-2
-    inject_tile(it, tile_z * it.tiles_x + tile_x, t - 2, out);
+    inject_tile(it, span_of(it.tile_off, tile_z * it.tiles_x + tile_x), t - 2, out);
 }
 
 // ============================================================== two steps per launch
@@ -465,8 +534,12 @@ struct Lds2 {
     static constexpr int W1 = kTileX + 2, H1 = TZ + 2, N1 = W1 * H1;   // tile grown by 1
     static constexpr int P0 = (N0 + kBlock - 1) / kBlock;               // per-thread shares
     static constexpr int P1 = (N1 + kBlock - 1) / kBlock;
-    // F0[N0] fields, C0[N0][2] coefficients, F1[N1] fields; adjoint also UA[N1], UB[N1]
-    static constexpr size_t bytes = ((size_t)N0 * (G + 2) + (size_t)N1 * G * (ADJ ? 3 : 1)) * sizeof(T);
+    static constexpr int ND = W0 + H0;                                  // damping: columns, then rows
+    static_assert(ND <= kBlock, "one damping value per thread");
+    // F0[N0] fields, C0[N0][2] coefficients, F1[N1] fields (adjoint: also
+    // UA[N1], UB[N1]), then D[ND] damping values of the grown tile
+    static constexpr size_t bytes =
+        ((size_t)N0 * (G + 2) + (size_t)N1 * G * (ADJ ? 3 : 1) + (size_t)ND) * sizeof(T);
 };
 
 template <typename T, int G, int R, bool ADJ>
@@ -475,6 +548,22 @@ __device__ __forceinline__ void cell_of(int c, int grow, int x0, int z0, int& ix
     const int W = kTileX + 2 * grow;
     ix = x0 - grow + c % W;
     iz = z0 - grow + c / W;
+}
+
+// Damping value e = D dt of column x0 - 2 + tid (tid < W0) or of row
+// z0 - 2 + (tid - W0) (W0 <= tid < ND) of the tile grown by two; zero outside
+// the grid.  Loaded with the burst so that the compute phase reads it from LDS.
+// (nx, nz and the profile pointers come in as values already held in scalar
+// registers: selecting them per lane through the descriptor would turn the
+// selection into a dependent vector load.)
+template <typename T, int W0, int ND>
+__device__ __forceinline__ T damping_of(const T* exd, const T* ezd, int nx, int nz, int tid, int x0, int z0)
+{
+    const bool col = tid < W0;
+    const int i = col ? x0 - 2 + tid : z0 - 2 + (tid - W0);
+    const bool in = tid < ND && i >= 0 && i < (col ? nx : nz);
+    const T v = ldg(col ? exd : ezd, in ? i : 0);
+    return in ? v : T(0);
 }
 
 template <typename T, int G, typename Acc, int R, int V = 0>
@@ -486,6 +575,7 @@ __device__ void tile_forward2(const Item<T, Acc>& it, const Step& st, int tile_x
     Vec<T, G>* U0 = reinterpret_cast<Vec<T, G>*>(smem);                  // u^n
     T* C0 = reinterpret_cast<T*>(U0 + L::N0);                            // (q, bt)
     Vec<T, G>* U1 = reinterpret_cast<Vec<T, G>*>(C0 + 2 * L::N0);        // u^{n+1}
+    T* D = reinterpret_cast<T*>(U1 + L::N1);                             // damping
     const T* cur = fwd_plane(it, st, n);
     const T* prev = fwd_plane(it, st, n - 1);
     T* out1 = it.seg + (int64_t)(n % it.K) * it.plane;
@@ -494,11 +584,16 @@ __device__ void tile_forward2(const Item<T, Acc>& it, const Step& st, int tile_x
     T* ck2 = ckpt_plane(it, st, n + 2);
     const Src<T, G> s1 = sources<T, G>(it, n);
     const Src<T, G> s2 = sources<T, G>(it, n + 1);
+    const Span rcv = sample ? span_of(it.tile_off, tile_z * it.tiles_x + tile_x) : Span{0, 0};
     const int x0 = tile_x * kTileX, z0 = tile_z * L::TZ;
     const int tid = threadIdx.y * kTileX + threadIdx.x;
     const T* cf = it.coef;
+    const T* exd_p = it.ex;
+    const T* ezd_p = it.ez;
 
-    // one burst: u^n and (q, bt) on the tile grown by 2, u^{n-1} on the tile grown by 1
+    // one burst: u^n and (q, bt) on the tile grown by 2, u^{n-1} on the tile
+    // grown by 1, the damping profile; cells outside the grid (or beyond the
+    // grown tile) load cell 0 and are replaced by zeros
     Vec<T, G> f0[L::P0], pv[L::P1];
     T q0[L::P0], b0[L::P0];
 #pragma unroll
@@ -507,10 +602,11 @@ __device__ void tile_forward2(const Item<T, Acc>& it, const Step& st, int tile_x
         int ix, iz;
         cell_of<T, G, R, false>(c, 2, x0, z0, ix, iz);
         const bool in = c < L::N0 && ix >= 0 && ix < nx && iz >= 0 && iz < nz;
-        const int64_t x = (int64_t)iz * nx + ix;
-        f0[i] = in ? vload<T, G>(cur, x) : vzero<T, G>();
-        q0[i] = in ? cf[2 * x] : T(0);
-        b0[i] = in ? cf[2 * x + 1] : T(0);
+        const int64_t x = in ? (int64_t)iz * nx + ix : 0;
+        f0[i] = vkeep<T, G>(in, vload<T, G>(cur, x));
+        const T q = ldg(cf, 2 * x), bt = ldg(cf, 2 * x + 1);
+        q0[i] = in ? q : T(0);
+        b0[i] = in ? bt : T(0);
     }
 #pragma unroll
     for (int i = 0; i < L::P1; ++i) {
@@ -518,8 +614,9 @@ __device__ void tile_forward2(const Item<T, Acc>& it, const Step& st, int tile_x
         int ix, iz;
         cell_of<T, G, R, false>(c, 1, x0, z0, ix, iz);
         const bool in = c < L::N1 && ix >= 0 && ix < nx && iz >= 0 && iz < nz;
-        pv[i] = in ? vload<T, G>(prev, (int64_t)iz * nx + ix) : vzero<T, G>();
+        pv[i] = vkeep<T, G>(in, vload<T, G>(prev, in ? (int64_t)iz * nx + ix : 0));
     }
+    const T dmp = damping_of<T, L::W0, L::ND>(exd_p, ezd_p, nx, nz, tid, x0, z0);
 #pragma unroll
     for (int i = 0; i < L::P0; ++i) {
         const int c = tid + i * kBlock;
@@ -529,6 +626,7 @@ __device__ void tile_forward2(const Item<T, Acc>& it, const Step& st, int tile_x
             C0[2 * c + 1] = b0[i];
         }
     }
+    if (tid < L::ND) D[tid] = dmp;
     __syncthreads();
     // step n on the tile grown by one cell
 #pragma unroll
@@ -544,7 +642,7 @@ __device__ void tile_forward2(const Item<T, Acc>& it, const Step& st, int tile_x
                 T fw, fe, fn, fs, a, b;
                 faces<T>(ix > 0, ix < nx - 1, iz > 0, iz < nz - 1, C0[2 * k + 1], C0[2 * (k - 1) + 1],
                          C0[2 * (k + 1) + 1], C0[2 * (k - L::W0) + 1], C0[2 * (k + L::W0) + 1], fw, fe, fn, fs);
-                damp_coeffs<T>(it.ex[ix] + it.ez[iz], a, b);
+                damp_coeffs<T>(D[ex + 1] + D[L::W0 + ez + 1], a, b);
                 const T q = C0[2 * k];
                 const Vec<T, G> u0 = U0[k], uw = U0[k - 1], ue = U0[k + 1], un = U0[k - L::W0], us = U0[k + L::W0];
 #pragma unroll
@@ -565,7 +663,7 @@ __device__ void tile_forward2(const Item<T, Acc>& it, const Step& st, int tile_x
     // step n+1 on the tile
     const int ix = x0 + (int)threadIdx.x;
     if (ix < nx) {
-        const T exd = it.ex[ix];
+        const T exd = D[threadIdx.x + 2];
 #pragma unroll
         for (int k = 0; k < R; ++k) {
             const int ez = (int)threadIdx.y * R + k, iz = z0 + ez;
@@ -576,7 +674,7 @@ __device__ void tile_forward2(const Item<T, Acc>& it, const Step& st, int tile_x
                 T fw, fe, fn, fs, a, b;
                 faces<T>(ix > 0, ix < nx - 1, iz > 0, iz < nz - 1, C0[2 * k0 + 1], C0[2 * (k0 - 1) + 1],
                          C0[2 * (k0 + 1) + 1], C0[2 * (k0 - L::W0) + 1], C0[2 * (k0 + L::W0) + 1], fw, fe, fn, fs);
-                damp_coeffs<T>(exd + it.ez[iz], a, b);
+                damp_coeffs<T>(exd + D[L::W0 + ez + 2], a, b);
                 const T q = C0[2 * k0];
                 const Vec<T, G> u0 = U1[k1], uw = U1[k1 - 1], ue = U1[k1 + 1], un = U1[k1 - L::W1],
                                 us = U1[k1 + L::W1];
@@ -593,7 +691,7 @@ __device__ void tile_forward2(const Item<T, Acc>& it, const Step& st, int tile_x
             }
         }
     }
-    if (sample) sample_tile(it, tile_z * it.tiles_x + tile_x, n, out1, out2);
+    sample_tile(it, rcv, n, out1, out2);
 }
 
 template <typename T, int G, typename Acc, int R, int V = 0>
@@ -607,6 +705,7 @@ __device__ void tile_adjoint2(const Item<T, Acc>& it, const Step& st, int tile_x
     Vec<T, G>* L1 = reinterpret_cast<Vec<T, G>*>(C0 + 2 * L::N0);        // lam^{t-1}, tile + 1
     Vec<T, G>* UA = L1 + L::N1;                                          // u^{t-1}, tile + 1
     Vec<T, G>* UB = UA + L::N1;                                          // u^{t-2}, tile + 1
+    T* D = reinterpret_cast<T*>(UB + L::N1);                             // damping
     const T* cur = it.lam + (int64_t)(t % nl) * P;
     const T* p1 = it.lam + (int64_t)((t + 1) % nl) * P;
     T* out1 = it.lam + (int64_t)((t - 1) % nl) * P;
@@ -616,34 +715,51 @@ __device__ void tile_adjoint2(const Item<T, Acc>& it, const Step& st, int tile_x
     const int x0 = tile_x * kTileX, z0 = tile_z * L::TZ;
     const int tid = threadIdx.y * kTileX + threadIdx.x;
     const int tile = tile_z * it.tiles_x + tile_x;
+    const Span rcv = span_of(it.tile_off, tile), rcv_x = span_of(it.tile_off_x, tile);
     const T* cf = it.coef;
+    const T* exd_p = it.ex;
+    const T* ezd_p = it.ez;
+    Acc* accK = it.acc;
+    Acc* accB = it.acc + ncell;
+    const int ix = x0 + (int)threadIdx.x;
 
     // one burst: lam^t and (q, bt) on the tile grown by 2; lam^{t+1}, u^{t-1},
-    // u^{t-2} on the tile grown by 1
+    // u^{t-2} on the tile grown by 1; the damping profile; this thread's
+    // imaging accumulators
     Vec<T, G> f0[L::P0], pv[L::P1], ua[L::P1], ub[L::P1];
     T q0[L::P0], b0[L::P0];
+    Acc sK[R], sB[R];
 #pragma unroll
     for (int i = 0; i < L::P0; ++i) {
         const int c = tid + i * kBlock;
-        int ix, iz;
-        cell_of<T, G, R, true>(c, 2, x0, z0, ix, iz);
-        const bool in = c < L::N0 && ix >= 0 && ix < nx && iz >= 0 && iz < nz;
-        const int64_t x = (int64_t)iz * nx + ix;
-        f0[i] = in ? vload<T, G>(cur, x) : vzero<T, G>();
-        q0[i] = in ? cf[2 * x] : T(0);
-        b0[i] = in ? cf[2 * x + 1] : T(0);
+        int ix0, iz0;
+        cell_of<T, G, R, true>(c, 2, x0, z0, ix0, iz0);
+        const bool in = c < L::N0 && ix0 >= 0 && ix0 < nx && iz0 >= 0 && iz0 < nz;
+        const int64_t x = in ? (int64_t)iz0 * nx + ix0 : 0;
+        f0[i] = vkeep<T, G>(in, vload<T, G>(cur, x));
+        const T q = ldg(cf, 2 * x), bt = ldg(cf, 2 * x + 1);
+        q0[i] = in ? q : T(0);
+        b0[i] = in ? bt : T(0);
     }
 #pragma unroll
     for (int i = 0; i < L::P1; ++i) {
         const int c = tid + i * kBlock;
-        int ix, iz;
-        cell_of<T, G, R, true>(c, 1, x0, z0, ix, iz);
-        const bool in = c < L::N1 && ix >= 0 && ix < nx && iz >= 0 && iz < nz;
-        const int64_t x = (int64_t)iz * nx + ix;
-        pv[i] = in ? vload<T, G>(p1, x) : vzero<T, G>();
-        ua[i] = in ? vload<T, G>(um1, x) : vzero<T, G>();
-        ub[i] = in ? vload<T, G>(um2, x) : vzero<T, G>();
+        int ix1, iz1;
+        cell_of<T, G, R, true>(c, 1, x0, z0, ix1, iz1);
+        const bool in = c < L::N1 && ix1 >= 0 && ix1 < nx && iz1 >= 0 && iz1 < nz;
+        const int64_t x = in ? (int64_t)iz1 * nx + ix1 : 0;
+        pv[i] = vkeep<T, G>(in, vload<T, G>(p1, x));
+        ua[i] = vkeep<T, G>(in, vload<T, G>(um1, x));
+        ub[i] = vkeep<T, G>(in, vload<T, G>(um2, x));
     }
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        const int iz = z0 + (int)threadIdx.y * R + k;
+        const int64_t x = ix < nx && iz < nz ? (int64_t)iz * nx + ix : 0;
+        sK[k] = ldg(accK, x);
+        sB[k] = ldg(accB, x);
+    }
+    const T dmp = damping_of<T, L::W0, L::ND>(exd_p, ezd_p, nx, nz, tid, x0, z0);
 #pragma unroll
     for (int i = 0; i < L::P0; ++i) {
         const int c = tid + i * kBlock;
@@ -661,6 +777,7 @@ __device__ void tile_adjoint2(const Item<T, Acc>& it, const Step& st, int tile_x
             UB[c] = ub[i];
         }
     }
+    if (tid < L::ND) D[tid] = dmp;
     __syncthreads();
     // lam^{t-1} on the tile grown by one cell
 #pragma unroll
@@ -668,14 +785,14 @@ __device__ void tile_adjoint2(const Item<T, Acc>& it, const Step& st, int tile_x
         const int c = tid + i * kBlock;
         if (c < L::N1) {
             const int ex = c % L::W1, ez = c / L::W1;
-            const int ix = x0 - 1 + ex, iz = z0 - 1 + ez;
+            const int ix1 = x0 - 1 + ex, iz1 = z0 - 1 + ez;
             Vec<T, G> r = vzero<T, G>();
-            if (ix >= 0 && ix < nx && iz >= 0 && iz < nz) {
+            if (ix1 >= 0 && ix1 < nx && iz1 >= 0 && iz1 < nz) {
                 const int k = (ez + 1) * L::W0 + ex + 1;
                 T fw, fe, fn, fs, a, b;
-                faces<T>(ix > 0, ix < nx - 1, iz > 0, iz < nz - 1, C0[2 * k + 1], C0[2 * (k - 1) + 1],
+                faces<T>(ix1 > 0, ix1 < nx - 1, iz1 > 0, iz1 < nz - 1, C0[2 * k + 1], C0[2 * (k - 1) + 1],
                          C0[2 * (k + 1) + 1], C0[2 * (k - L::W0) + 1], C0[2 * (k + L::W0) + 1], fw, fe, fn, fs);
-                damp_coeffs<T>(it.ex[ix] + it.ez[iz], a, b);
+                damp_coeffs<T>(D[ex + 1] + D[L::W0 + ez + 1], a, b);
                 const T qc = C0[2 * k], qw = C0[2 * (k - 1)], qe = C0[2 * (k + 1)], qn = C0[2 * (k - L::W0)],
                         qs = C0[2 * (k + L::W0)];
                 const Vec<T, G> l0 = L0[k], lw = L0[k - 1], le = L0[k + 1], ln = L0[k - L::W0], ls = L0[k + L::W0];
@@ -689,14 +806,13 @@ __device__ void tile_adjoint2(const Item<T, Acc>& it, const Step& st, int tile_x
     }
     // adjoint source of lam^{t-1} (sample t-2) at the receivers of the grown tile
     {
-        const int e0 = it.tile_off_x[tile], e1 = it.tile_off_x[tile + 1];
         __syncthreads();
-        if (e1 > e0 && has_adj_source(it)) {
-            for (int e = e0 + tid; e < e1; e += kBlock) {
-                const Entry en = it.entries_x[e];
+        if (rcv_x.e1 > rcv_x.e0 && has_adj_source(it)) {
+            for (int e = rcv_x.e0 + tid; e < rcv_x.e1; e += kBlock) {
+                const Entry en = ld_entry(it.entries_x, e);
                 if (en.run == 0) continue;
                 T sum = T(0);
-                for (int k = 0; k < en.run; ++k) sum += adj_source(it, it.entries_x[e + k], t - 2);
+                for (int k = 0; k < en.run; ++k) sum += adj_source(it, ld_entry(it.entries_x, e + k), t - 2);
                 const int cell = en.slot / G, g = en.slot - cell * G;
                 const int ex = cell % nx - (x0 - 1), ez = cell / nx - (z0 - 1);
                 L1[ez * L::W1 + ex].v[g] += sum;
@@ -705,14 +821,11 @@ __device__ void tile_adjoint2(const Item<T, Acc>& it, const Step& st, int tile_x
         }
     }
     // on the tile: imaging of (lam^t, u^{t-1}), lam^{t-2}, imaging of (lam^{t-1}, u^{t-2})
-    const int ix = x0 + (int)threadIdx.x;
     if (ix < nx) {
-        const T exd = it.ex[ix];
+        const T exd = D[threadIdx.x + 2];
         const bool hw = ix > 0, he = ix < nx - 1;
         const T hf = T(0.5);
         const T cw = hw ? hf : T(1), ce = he ? hf : T(1);
-        Acc* accK = it.acc;
-        Acc* accB = it.acc + ncell;
 #pragma unroll
         for (int k = 0; k < R; ++k) {
             const int ez = (int)threadIdx.y * R + k, iz = z0 + ez;
@@ -725,7 +838,7 @@ __device__ void tile_adjoint2(const Item<T, Acc>& it, const Step& st, int tile_x
                 faces<T>(hw, he, hn, hs, C0[2 * k0 + 1], C0[2 * (k0 - 1) + 1], C0[2 * (k0 + 1) + 1],
                          C0[2 * (k0 - L::W0) + 1], C0[2 * (k0 + L::W0) + 1], fw, fe, fn, fs);
                 const T cn = hn ? hf : T(1), cs = hs ? hf : T(1);
-                damp_coeffs<T>(exd + it.ez[iz], a, b);
+                damp_coeffs<T>(exd + D[L::W0 + ez + 2], a, b);
                 const T qc = C0[2 * k0], qw = C0[2 * (k0 - 1)], qe = C0[2 * (k0 + 1)], qn = C0[2 * (k0 - L::W0)],
                         qs = C0[2 * (k0 + L::W0)];
                 const Vec<T, G> l0 = L0[k0], lw = L0[k0 - 1], le = L0[k0 + 1], ln = L0[k0 - L::W0],
@@ -759,18 +872,18 @@ __device__ void tile_adjoint2(const Item<T, Acc>& it, const Step& st, int tile_x
                 }
                 vstore<T, G>(out1, x, m0);
                 vstore<T, G>(out2, x, r);
-                Acc vk = accK[x], vb = accB[x];
+                Acc vk = sK[k], vb = sB[k];
                 vk += ska;
                 vb += sba;
                 vk += skb;
                 vb += sbb;
-                accK[x] = vk;
-                accB[x] = vb;
+                stg(accK, x, vk);
+                stg(accB, x, vb);
             }
         }
     }
     // adjoint source of lam^{t-2}: sample t-3
-    inject_tile(it, tile, t - 3, out2);
+    inject_tile(it, rcv, t - 3, out2);
 }
 
 // Item position at launch s of a call (mode shifts / limits the schedule).
