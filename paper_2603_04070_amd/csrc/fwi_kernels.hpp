@@ -58,15 +58,17 @@ struct Item {
     int32_t nx, nz, nt, g_used;      // g_used <= G real transmits
     int32_t K, J, tiles_x, n_tiles;
     int32_t n_rcv, tx0, inject_adj, sample;   // inject_adj: 1 if d_adj drives the adjoint
-    int32_t S, nlam, pad0, pad1;     // steps fused per launch; lambda planes (lam^tau in tau mod nlam)
+    int32_t S, nlam;                 // steps fused per launch; lambda planes (lam^tau in tau mod nlam)
+    int32_t keep_from, pad1;         // first level the adjoint reads from the first forward pass
     int64_t plane;                   // elements per field plane = nx*nz*G
     int64_t wavelet_stride;
     const T* coef;                   // [nz*nx] x (Q, bt)
     const T* ex;                     // [nx]  Dx(ix) dt
     const T* ez;                     // [nz]  Dz(iz) dt
     T* seg;                          // K planes
-    T* ck;                           // 2 (J-1) planes: pair j >= 1 at 2(j-1): prev, cur
-    T* lam;                          // 2 planes
+    T* ck;                           // 2 (J-1) planes: pair of segment j >= 1 at 2(j-1): v^{jK}, u^{jK}
+    T* lam;                          // nlam planes
+    T* vel;                          // 2 planes: v^tau = u^tau - u^{tau-1} in slot (tau / 2) mod 2
     Acc* acc;                        // [2][nz*nx]: S_kappa, S_b
     const T* zero;                   // zero plane
     const T* wavelet;                // transmit tx row at wavelet + tx * wavelet_stride
@@ -221,16 +223,38 @@ __device__ __forceinline__ void damp_coeffs(T e, T& a, T& b)
     }
 }
 
-// One cell of the forward update: a u0 + b up + q sum_f b_f (u_f - u0).
+// Forward update in increment form.  With v^n = u^n - u^{n-1} the update of
+// eq. 2, u^{n+1} = a u^n + beta u^{n-1} + q L u^n, is the same map written as
+//     v^{n+1} = -beta v^n + c2 u^n + q L u^n,   u^{n+1} = u^n + v^{n+1},
+// with c2 = a + beta - 1 = -e^2/(1+e) (e = D dt); inside the absorbing layer's
+// inner edge -beta = 1 and c2 = 0.  In floating point the two forms differ:
+// the rounding error of each step enters u^{n+1} and, through the two-level
+// recurrence, is summed twice over time in the first form but once in the
+// second, which matters for the slowly varying late part of the field.
 template <typename T>
-__device__ __forceinline__ T fwd_cell(T a, T b, T q, T fw, T fe, T fn, T fs, T u0, T uw, T ue, T un, T us, T up)
+__device__ __forceinline__ void damp_inc(T e, T& nb, T& c2)
+{
+#pragma clang fp contract(off)
+    if (e == T(0)) {
+        nb = T(1);
+        c2 = T(0);
+    } else {
+        const T inv = T(1) / (T(1) + e);
+        nb = (T(1) - e) * inv;
+        c2 = -(e * e) * inv;
+    }
+}
+
+// v^{n+1} of one cell (before the source): -beta v0 + c2 u0 + q sum_f b_f (u_f - u0).
+template <typename T>
+__device__ __forceinline__ T fwd_cell(T nb, T c2, T q, T fw, T fe, T fn, T fs, T u0, T uw, T ue, T un, T us, T v0)
 {
 #pragma clang fp contract(off)
     T L = fw * (uw - u0);
     L = fma(fe, ue - u0, L);
     L = fma(fn, un - u0, L);
     L = fma(fs, us - u0, L);
-    return fma(q, L, fma(b, up, a * u0));
+    return fma(q, L, fma(nb, v0, c2 * u0));
 }
 
 // One cell of the adjoint update: a l0 + b lp + sum_f b_f (w_f - w0), w = q l.
@@ -278,44 +302,45 @@ __device__ __forceinline__ void faces(bool hw, bool he, bool hn, bool hs, T bc, 
     fs = hs ? hf * (bc + bs) : bc;
 }
 
-// Plane of u^tau for a forward-type step: zero for tau <= 0; on recompute,
-// the checkpoint pair of segment j for tau <= jK; else segment slot (tau-1) mod K.
+// Plane of u^tau read by a forward-type step: zero for tau = 0; on
+// recompute, the checkpoint of segment j for tau = jK; else segment slot
+// (tau-1) mod K.
 template <typename T, typename Acc>
 __device__ __forceinline__ const T* fwd_plane(const Item<T, Acc>& it, const Step& st, int tau)
 {
     if (tau <= 0) return it.zero;
-    if (st.phase == kRecomp && tau <= st.j * it.K)
-        return it.ck + (int64_t)(2 * (st.j - 1) + (tau == st.j * it.K ? 1 : 0)) * it.plane;
+    if (st.phase == kRecomp && tau == st.j * it.K) return it.ck + (int64_t)(2 * (st.j - 1) + 1) * it.plane;
     return it.seg + (int64_t)((tau - 1) % it.K) * it.plane;
 }
 
-// Checkpoint plane that u^{t1} is also written to during the first forward pass, or null.
+// Plane of v^tau read by a forward-type step: zero for tau = 0; on
+// recompute, the checkpoint of segment j for tau = jK; else its v slot.  A
+// two-step launch reads slot(n) and writes slot(n+2), which always differ; a
+// one-step launch reads and writes one cell's value in place or across slots.
 template <typename T, typename Acc>
-__device__ __forceinline__ T* ckpt_plane(const Item<T, Acc>& it, const Step& st, int t1)
+__device__ __forceinline__ const T* vel_in(const Item<T, Acc>& it, const Step& st, int tau)
 {
-    if (st.phase != kFwd) return nullptr;
-    const int jn = (t1 - 1) / it.K + 1;   // segment after the one holding u^{t1}
-    if (jn > it.J - 1) return nullptr;
-    if (t1 == jn * it.K - 1) return it.ck + (int64_t)(2 * (jn - 1)) * it.plane;
-    if (t1 == jn * it.K) return it.ck + (int64_t)(2 * (jn - 1) + 1) * it.plane;
-    return nullptr;
+    if (tau <= 0) return it.zero;
+    if (st.phase == kRecomp && tau == st.j * it.K) return it.ck + (int64_t)(2 * (st.j - 1)) * it.plane;
+    return it.vel + (int64_t)((tau >> 1) & 1) * it.plane;
 }
 
-__device__ __forceinline__ Entry ld_entry(const Entry* p, int i)
+template <typename T, typename Acc>
+__device__ __forceinline__ T* vel_out(const Item<T, Acc>& it, int tau)
 {
-    typedef int32_t I4 __attribute__((ext_vector_type(4)));
-    const I4 v = ((const I4 __attribute__((address_space(1)))*)p)[i];
-    return Entry{v[0], v[1], v[2], v[3]};
+    return it.vel + (int64_t)((tau >> 1) & 1) * it.plane;
 }
 
-// Receiver entries [e0, e1) of one tile.
-struct Span {
-    int e0, e1;
-};
-
-__device__ __forceinline__ Span span_of(const int32_t* off, int tile)
+// Checkpoint pair that level t1 = jK (1 <= j <= J-1, the start of segment j)
+// is also written to during the first forward pass: v^{t1} at the pair's
+// first plane, u^{t1} at its second; null for every other level.
+template <typename T, typename Acc>
+__device__ __forceinline__ T* ckpt_pair(const Item<T, Acc>& it, const Step& st, int t1)
 {
-    return Span{ldg(off, tile), ldg(off, tile + 1)};
+    if (st.phase != kFwd || t1 % it.K != 0) return nullptr;
+    const int j = t1 / it.K;
+    if (j < 1 || j > it.J - 1) return nullptr;
+    return it.ck + (int64_t)(2 * (j - 1)) * it.plane;
 }
 
 template <typename T, int G>
@@ -336,6 +361,23 @@ __device__ __forceinline__ Src<T, G> sources(const Item<T, Acc>& it, int n)
     return s;
 }
 
+__device__ __forceinline__ Entry ld_entry(const Entry* p, int i)
+{
+    typedef int32_t I4 __attribute__((ext_vector_type(4)));
+    const I4 v = ((const I4 __attribute__((address_space(1)))*)p)[i];
+    return Entry{v[0], v[1], v[2], v[3]};
+}
+
+// Receiver entries [e0, e1) of one tile.
+struct Span {
+    int e0, e1;
+};
+
+__device__ __forceinline__ Span span_of(const int32_t* off, int tile)
+{
+    return Span{ldg(off, tile), ldg(off, tile + 1)};
+}
+
 // Traces d[n] (and d[n+1] from out2) at the receivers of one tile, read back
 // after the whole workgroup has stored its cells.
 template <typename T, typename Acc>
@@ -348,6 +390,24 @@ __device__ __forceinline__ void sample_tile(const Item<T, Acc>& it, Span sp, int
         const Entry en = ld_entry(it.entries, e);
         stg(it.traces, en.trace_off + (int64_t)n * it.n_rcv, ldg(out, en.slot));
         if (out2) stg(it.traces, en.trace_off + (int64_t)(n + 1) * it.n_rcv, ldg(out2, en.slot));
+    }
+}
+
+// Traces d[n] from the LDS copy of u^{n+1} (tile grown by one, row width W1)
+// and d[n+1] from the stored u^{n+2}, at the receivers of one tile.
+template <typename T, int G, typename Acc>
+__device__ __forceinline__ void sample_tile2(const Item<T, Acc>& it, Span sp, int n, const Vec<T, G>* U1, int W1,
+                                             int x0, int z0, const T* out2)
+{
+    if (sp.e1 <= sp.e0) return;
+    __syncthreads();
+    const int tid = threadIdx.y * kTileX + threadIdx.x;
+    for (int e = sp.e0 + tid; e < sp.e1; e += kBlock) {
+        const Entry en = ld_entry(it.entries, e);
+        const int cell = en.slot / G, g = en.slot - cell * G;
+        const int k = (cell / it.nx - z0 + 1) * W1 + (cell % it.nx - x0 + 1);
+        stg(it.traces, en.trace_off + (int64_t)n * it.n_rcv, U1[k].v[g]);
+        stg(it.traces, en.trace_off + (int64_t)(n + 1) * it.n_rcv, ldg(out2, en.slot));
     }
 }
 
@@ -395,9 +455,11 @@ __device__ void tile_forward(const Item<T, Acc>& it, const Step& st, int tile_x,
 {
     const int nx = it.nx, nz = it.nz, n = st.n;
     const T* cur = fwd_plane(it, st, n);
-    const T* prev = fwd_plane(it, st, n - 1);
+    const T* vin = vel_in(it, st, n);
     T* out = it.seg + (int64_t)(n % it.K) * it.plane;
-    T* ck_out = ckpt_plane(it, st, n + 1);
+    T* vout = vel_out(it, n + 1);
+    T* ckv = ckpt_pair(it, st, n + 1);
+    T* cku = ckv ? ckv + it.plane : nullptr;
     const Src<T, G> src = sources<T, G>(it, n);
 
     const int ix = tile_x * kTileX + (int)threadIdx.x;
@@ -423,18 +485,23 @@ __device__ void tile_forward(const Item<T, Acc>& it, const Step& st, int tile_x,
             const T be = he ? ldg(cf, 2 * (x + 1) + 1) : T(0);
             T fw, fe, fn, fs;
             faces<T>(hw, he, iz > 0, hs, bc, bw, be, bn, bs, fw, fe, fn, fs);
-            T a, b;
-            damp_coeffs<T>(ex + ldg(it.ez, iz), a, b);
-            const Vec<T, G> up = vload<T, G>(prev, x);
-            Vec<T, G> r;
+            T nb, c2;
+            damp_inc<T>(ex + ldg(it.ez, iz), nb, c2);
+            const Vec<T, G> vp = vload<T, G>(vin, x);
+            Vec<T, G> r, rv;
 #pragma unroll
             for (int g = 0; g < G; ++g) {
-                T v = fwd_cell<T>(a, b, q, fw, fe, fn, fs, uc.v[g], uw.v[g], ue.v[g], un.v[g], us.v[g], up.v[g]);
+                T v = fwd_cell<T>(nb, c2, q, fw, fe, fn, fs, uc.v[g], uw.v[g], ue.v[g], un.v[g], us.v[g], vp.v[g]);
                 if ((int)x == src.cell[g]) v += src.w[g];
-                r.v[g] = v;
+                rv.v[g] = v;
+                r.v[g] = uc.v[g] + v;
             }
             vstore<T, G>(out, x, r);
-            if (ck_out) vstore<T, G>(ck_out, x, r);
+            vstore<T, G>(vout, x, rv);
+            if (ckv) {
+                vstore<T, G>(cku, x, r);
+                vstore<T, G>(ckv, x, rv);
+            }
             un = uc; uc = us;
             bn = bc; bc = bs; q = qs;
         }
@@ -566,56 +633,79 @@ __device__ __forceinline__ T damping_of(const T* exd, const T* ezd, int nx, int 
     return in ? v : T(0);
 }
 
+// Cell (ex, ez) of the ring of the tile grown by one (ring index r < NR):
+// top row, bottom row, left column, right column.
+template <int W1, int TZ>
+__device__ __forceinline__ void ring_cell(int r, int& ex, int& ez)
+{
+    if (r < W1) { ex = r; ez = 0; }
+    else if (r < 2 * W1) { ex = r - W1; ez = TZ + 1; }
+    else if (r < 2 * W1 + TZ) { ex = 0; ez = 1 + r - 2 * W1; }
+    else { ex = W1 - 1; ez = 1 + r - 2 * W1 - TZ; }
+}
+
 template <typename T, int G, typename Acc, int R, int V = 0>
 __device__ void tile_forward2(const Item<T, Acc>& it, const Step& st, int tile_x, int tile_z, bool sample,
                               unsigned char* smem)
 {
     using L = Lds2<T, G, R, false>;
+    constexpr int NR = 2 * L::W1 + 2 * L::TZ;                            // ring cells of the tile grown by 1
+    static_assert(NR <= kBlock, "one ring cell per thread");
     const int nx = it.nx, nz = it.nz, n = st.n;
-    Vec<T, G>* U0 = reinterpret_cast<Vec<T, G>*>(smem);                  // u^n
-    T* C0 = reinterpret_cast<T*>(U0 + L::N0);                            // (q, bt)
-    Vec<T, G>* U1 = reinterpret_cast<Vec<T, G>*>(C0 + 2 * L::N0);        // u^{n+1}
+    Vec<T, G>* U0 = reinterpret_cast<Vec<T, G>*>(smem);                  // u^n, tile + 2
+    T* C0 = reinterpret_cast<T*>(U0 + L::N0);                            // (q, bt), tile + 2
+    Vec<T, G>* U1 = reinterpret_cast<Vec<T, G>*>(C0 + 2 * L::N0);        // u^{n+1}, tile + 1
     T* D = reinterpret_cast<T*>(U1 + L::N1);                             // damping
     const T* cur = fwd_plane(it, st, n);
-    const T* prev = fwd_plane(it, st, n - 1);
+    const T* vin = vel_in(it, st, n);
     T* out1 = it.seg + (int64_t)(n % it.K) * it.plane;
     T* out2 = it.seg + (int64_t)((n + 1) % it.K) * it.plane;
-    T* ck1 = ckpt_plane(it, st, n + 1);
-    T* ck2 = ckpt_plane(it, st, n + 2);
+    T* vout = vel_out(it, n + 2);
+    T* ck1 = ckpt_pair(it, st, n + 1);
+    T* ck2 = ckpt_pair(it, st, n + 2);
+    // u^{n+1} is the next launch's input only when this launch stops there;
+    // in a two-step launch it is stored only where the adjoint will read it
+    // (every recomputed level, and the first pass's levels from the last
+    // segment on)
+    const bool keep1 = st.phase != kFwd || n + 1 >= it.keep_from;
     const Src<T, G> s1 = sources<T, G>(it, n);
     const Src<T, G> s2 = sources<T, G>(it, n + 1);
     const Span rcv = sample ? span_of(it.tile_off, tile_z * it.tiles_x + tile_x) : Span{0, 0};
     const int x0 = tile_x * kTileX, z0 = tile_z * L::TZ;
     const int tid = threadIdx.y * kTileX + threadIdx.x;
+    const int ix = x0 + (int)threadIdx.x;
     const T* cf = it.coef;
     const T* exd_p = it.ex;
     const T* ezd_p = it.ez;
 
-    // one burst: u^n and (q, bt) on the tile grown by 2, u^{n-1} on the tile
-    // grown by 1, the damping profile; cells outside the grid (or beyond the
-    // grown tile) load cell 0 and are replaced by zeros
-    Vec<T, G> f0[L::P0], pv[L::P1];
+    // one burst: u^n and (q, bt) on the tile grown by 2; v^n at this lane's
+    // tile cells and ring cell; the damping profile.  Cells outside the grid
+    // (or beyond the grown tile) load cell 0 and are replaced by zeros.
+    Vec<T, G> f0[L::P0], vt[R], vr;
     T q0[L::P0], b0[L::P0];
 #pragma unroll
     for (int i = 0; i < L::P0; ++i) {
         const int c = tid + i * kBlock;
-        int ix, iz;
-        cell_of<T, G, R, false>(c, 2, x0, z0, ix, iz);
-        const bool in = c < L::N0 && ix >= 0 && ix < nx && iz >= 0 && iz < nz;
-        const int64_t x = in ? (int64_t)iz * nx + ix : 0;
+        int gx, gz;
+        cell_of<T, G, R, false>(c, 2, x0, z0, gx, gz);
+        const bool in = c < L::N0 && gx >= 0 && gx < nx && gz >= 0 && gz < nz;
+        const int64_t x = in ? (int64_t)gz * nx + gx : 0;
         f0[i] = vkeep<T, G>(in, vload<T, G>(cur, x));
         const T q = ldg(cf, 2 * x), bt = ldg(cf, 2 * x + 1);
         q0[i] = in ? q : T(0);
         b0[i] = in ? bt : T(0);
     }
 #pragma unroll
-    for (int i = 0; i < L::P1; ++i) {
-        const int c = tid + i * kBlock;
-        int ix, iz;
-        cell_of<T, G, R, false>(c, 1, x0, z0, ix, iz);
-        const bool in = c < L::N1 && ix >= 0 && ix < nx && iz >= 0 && iz < nz;
-        pv[i] = vkeep<T, G>(in, vload<T, G>(prev, in ? (int64_t)iz * nx + ix : 0));
+    for (int k = 0; k < R; ++k) {
+        const int iz = z0 + (int)threadIdx.y * R + k;
+        const bool in = ix < nx && iz < nz;
+        vt[k] = vkeep<T, G>(in, vload<T, G>(vin, in ? (int64_t)iz * nx + ix : 0));
     }
+    int rex = 0, rez = 0;
+    ring_cell<L::W1, L::TZ>(tid, rex, rez);
+    const int rix = x0 - 1 + rex, riz = z0 - 1 + rez;
+    const bool rin = tid < NR && rix >= 0 && rix < nx && riz >= 0 && riz < nz;
+    vr = vkeep<T, G>(rin, vload<T, G>(vin, rin ? (int64_t)riz * nx + rix : 0));
     const T dmp = damping_of<T, L::W0, L::ND>(exd_p, ezd_p, nx, nz, tid, x0, z0);
 #pragma unroll
     for (int i = 0; i < L::P0; ++i) {
@@ -628,40 +718,50 @@ __device__ void tile_forward2(const Item<T, Acc>& it, const Step& st, int tile_x
     }
     if (tid < L::ND) D[tid] = dmp;
     __syncthreads();
-    // step n on the tile grown by one cell
+
+    // step n at cell (ex, ez) of the tile grown by one: v^{n+1} into vv (v^n
+    // given there), u^{n+1} returned; the caller knows the cell is in the grid
+    auto step1 = [&](int ex, int ez, int gx, int gz, Vec<T, G>& vv) {
+        const int k = (ez + 1) * L::W0 + ex + 1;
+        const int64_t x = (int64_t)gz * nx + gx;
+        T fw, fe, fn, fs, nb, c2;
+        faces<T>(gx > 0, gx < nx - 1, gz > 0, gz < nz - 1, C0[2 * k + 1], C0[2 * (k - 1) + 1],
+                 C0[2 * (k + 1) + 1], C0[2 * (k - L::W0) + 1], C0[2 * (k + L::W0) + 1], fw, fe, fn, fs);
+        damp_inc<T>(D[ex + 1] + D[L::W0 + ez + 1], nb, c2);
+        const T q = C0[2 * k];
+        const Vec<T, G> u0 = U0[k], uw = U0[k - 1], ue = U0[k + 1], un = U0[k - L::W0], us = U0[k + L::W0];
+        Vec<T, G> r;
 #pragma unroll
-    for (int i = 0; i < L::P1; ++i) {
-        const int c = tid + i * kBlock;
-        if (c < L::N1) {
-            const int ex = c % L::W1, ez = c / L::W1;
-            const int ix = x0 - 1 + ex, iz = z0 - 1 + ez;
-            Vec<T, G> r = vzero<T, G>();
-            if (ix >= 0 && ix < nx && iz >= 0 && iz < nz) {
-                const int k = (ez + 1) * L::W0 + ex + 1;
-                const int64_t x = (int64_t)iz * nx + ix;
-                T fw, fe, fn, fs, a, b;
-                faces<T>(ix > 0, ix < nx - 1, iz > 0, iz < nz - 1, C0[2 * k + 1], C0[2 * (k - 1) + 1],
-                         C0[2 * (k + 1) + 1], C0[2 * (k - L::W0) + 1], C0[2 * (k + L::W0) + 1], fw, fe, fn, fs);
-                damp_coeffs<T>(D[ex + 1] + D[L::W0 + ez + 1], a, b);
-                const T q = C0[2 * k];
-                const Vec<T, G> u0 = U0[k], uw = U0[k - 1], ue = U0[k + 1], un = U0[k - L::W0], us = U0[k + L::W0];
+        for (int g = 0; g < G; ++g) {
+            T v = fwd_cell<T>(nb, c2, q, fw, fe, fn, fs, u0.v[g], uw.v[g], ue.v[g], un.v[g], us.v[g], vv.v[g]);
+            if ((int)x == s1.cell[g]) v += s1.w[g];
+            vv.v[g] = v;
+            r.v[g] = u0.v[g] + v;
+        }
+        return r;
+    };
+    // step n: the ring (u^{n+1} to LDS only), then the tile cells of this
+    // lane, with the map of step n+1, so that v^{n+1} stays in registers
+    if (tid < NR) U1[rez * L::W1 + rex] = rin ? step1(rex, rez, rix, riz, vr) : vzero<T, G>();
 #pragma unroll
-                for (int g = 0; g < G; ++g) {
-                    T v = fwd_cell<T>(a, b, q, fw, fe, fn, fs, u0.v[g], uw.v[g], ue.v[g], un.v[g], us.v[g], pv[i].v[g]);
-                    if ((int)x == s1.cell[g]) v += s1.w[g];
-                    r.v[g] = v;
-                }
-                if (ex >= 1 && ex <= kTileX && ez >= 1 && ez <= L::TZ) {
-                    vstore<T, G>(out1, x, r);
-                    if (ck1) vstore<T, G>(ck1, x, r);
-                }
+    for (int k = 0; k < R; ++k) {
+        const int ez = (int)threadIdx.y * R + k, iz = z0 + ez;
+        const int k1 = (ez + 1) * L::W1 + threadIdx.x + 1;
+        if (ix < nx && iz < nz) {
+            const Vec<T, G> r = step1((int)threadIdx.x + 1, ez + 1, ix, iz, vt[k]);
+            const int64_t x = (int64_t)iz * nx + ix;
+            if (keep1) vstore<T, G>(out1, x, r);
+            if (ck1) {
+                vstore<T, G>(ck1, x, vt[k]);
+                vstore<T, G>(ck1 + it.plane, x, r);
             }
-            U1[c] = r;
+            U1[k1] = r;
+        } else {
+            U1[k1] = vzero<T, G>();
         }
     }
     __syncthreads();
     // step n+1 on the tile
-    const int ix = x0 + (int)threadIdx.x;
     if (ix < nx) {
         const T exd = D[threadIdx.x + 2];
 #pragma unroll
@@ -671,27 +771,31 @@ __device__ void tile_forward2(const Item<T, Acc>& it, const Step& st, int tile_x
                 const int k1 = (ez + 1) * L::W1 + threadIdx.x + 1;
                 const int k0 = (ez + 2) * L::W0 + threadIdx.x + 2;
                 const int64_t x = (int64_t)iz * nx + ix;
-                T fw, fe, fn, fs, a, b;
+                T fw, fe, fn, fs, nb, c2;
                 faces<T>(ix > 0, ix < nx - 1, iz > 0, iz < nz - 1, C0[2 * k0 + 1], C0[2 * (k0 - 1) + 1],
                          C0[2 * (k0 + 1) + 1], C0[2 * (k0 - L::W0) + 1], C0[2 * (k0 + L::W0) + 1], fw, fe, fn, fs);
-                damp_coeffs<T>(exd + D[L::W0 + ez + 2], a, b);
+                damp_inc<T>(exd + D[L::W0 + ez + 2], nb, c2);
                 const T q = C0[2 * k0];
                 const Vec<T, G> u0 = U1[k1], uw = U1[k1 - 1], ue = U1[k1 + 1], un = U1[k1 - L::W1],
                                 us = U1[k1 + L::W1];
-                const Vec<T, G> up = U0[k0];
-                Vec<T, G> r;
+                Vec<T, G> r, rv;
 #pragma unroll
                 for (int g = 0; g < G; ++g) {
-                    T v = fwd_cell<T>(a, b, q, fw, fe, fn, fs, u0.v[g], uw.v[g], ue.v[g], un.v[g], us.v[g], up.v[g]);
+                    T v = fwd_cell<T>(nb, c2, q, fw, fe, fn, fs, u0.v[g], uw.v[g], ue.v[g], un.v[g], us.v[g], vt[k].v[g]);
                     if ((int)x == s2.cell[g]) v += s2.w[g];
-                    r.v[g] = v;
+                    rv.v[g] = v;
+                    r.v[g] = u0.v[g] + v;
                 }
                 vstore<T, G>(out2, x, r);
-                if (ck2) vstore<T, G>(ck2, x, r);
+                vstore<T, G>(vout, x, rv);
+                if (ck2) {
+                    vstore<T, G>(ck2, x, rv);
+                    vstore<T, G>(ck2 + it.plane, x, r);
+                }
             }
         }
     }
-    sample_tile(it, rcv, n, out1, out2);
+    sample_tile2<T, G>(it, rcv, n, U1, L::W1, x0, z0, out2);
 }
 
 template <typename T, int G, typename Acc, int R, int V = 0>

@@ -35,7 +35,7 @@ struct ItemPlan {
     int tiles_x, tiles_z, n_tiles;
     int blk0;                  // first block of this item in the block table
     int steps;                 // schedule length 2T + K(J-1)
-    size_t seg_off, ck_off, lam_off, acc_off;   // workspace byte offsets
+    size_t seg_off, ck_off, lam_off, vel_off, acc_off;   // workspace byte offsets
     size_t src_off, tile_off_off, entry_off;    // plan-table byte offsets
     size_t tile_off_x_off, entry_x_off;         // receivers of each tile grown by one cell
 };
@@ -509,7 +509,8 @@ static fwi_status create_impl(fwi_plan* p, fwi_dtype dtype, const fwi_grid* grid
     auto state_bytes = [&](const ItemPlan& it, int K) {
         const int T = p->media[it.medium].g.nt;
         const int J = o.forward_only ? 1 : (T + K - 1) / K;
-        return plane_bytes(it) * (size_t)(K + 2 * (J - 1) + 4);
+        // segment K + checkpoints 2 (J-1) + up to 4 lambda planes + 2 v planes
+        return plane_bytes(it) * (size_t)(K + 2 * (J - 1) + 6);
     };
     auto auto_k = [&](int T) {
         if (T <= 2) return T;
@@ -614,7 +615,7 @@ static fwi_status create_impl(fwi_plan* p, fwi_dtype dtype, const fwi_grid* grid
 
     // ---------------- workspace layout:
     // [zero plane][accumulators][misfit partials][coefficients][state of one wave]
-    // with a wave's state laid out as [lambda planes of its items][checkpoints][segments]
+    // with a wave's state laid out as [lambda planes of its items][checkpoints][segments][v planes]
     size_t off = 0;
     size_t zmax = 0;
     for (auto& it : p->items) zmax = std::max(zmax, plane_bytes(it));
@@ -639,6 +640,7 @@ static fwi_status create_impl(fwi_plan* p, fwi_dtype dtype, const fwi_grid* grid
         w.lam_bytes = o2 - w.lam_off;
         for (int i : w.items) { p->items[i].ck_off = o2; o2 += plane_bytes(p->items[i]) * 2 * (size_t)(p->items[i].J - 1); }
         for (int i : w.items) { p->items[i].seg_off = o2; o2 += plane_bytes(p->items[i]) * (size_t)p->items[i].K; }
+        for (int i : w.items) { p->items[i].vel_off = o2; o2 += plane_bytes(p->items[i]) * 2; }
         state_max = std::max(state_max, o2 - state_off);
         w.steps = w.fwd = w.adj = 0;
         for (int i : w.items) {
@@ -912,6 +914,7 @@ void fill_descriptors(fwi_plan* p, const fwi_io* io, unsigned char* ws, bool adj
         d.seg = reinterpret_cast<T*>(ws + ip.seg_off);
         d.ck = reinterpret_cast<T*>(ws + ip.ck_off);
         d.lam = reinterpret_cast<T*>(ws + ip.lam_off);
+        d.vel = reinterpret_cast<T*>(ws + ip.vel_off);
         d.acc = reinterpret_cast<Acc*>(ws + ip.acc_off);
         d.zero = reinterpret_cast<const T*>(ws + p->zero_off);
         d.wavelet = reinterpret_cast<const T*>(mio.wavelet);
@@ -925,6 +928,8 @@ void fill_descriptors(fwi_plan* p, const fwi_io* io, unsigned char* ws, bool adj
         d.entries_x = reinterpret_cast<const Entry*>(tabs + ip.entry_x_off);
         d.S = p->S;
         d.nlam = p->nlam;
+        // the adjoint of the last segment reads levels (J-1)K + 1 .. T of the first pass
+        d.keep_from = p->opt.forward_only ? INT_MAX : (ip.J - 1) * ip.K + 1;
         items[i] = d;
     }
     for (size_t i = 0; i < p->media.size(); ++i) {
