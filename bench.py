@@ -37,7 +37,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="uneven64", choices=["uneven64", "rodgauss512", "disc128", "unfold16"])
+    ap.add_argument("--workload", default="uneven64", choices=["uneven64", "rodgauss512", "disc128", "ring188", "unfold16"])
     ap.add_argument("--unfold-k", type=int, default=8, help="unfolded iterations (unfold16)")
     ap.add_argument("--unfold-backprop", default="fd", choices=["none", "fd"])
     ap.add_argument("--media", type=int, default=64, help="media of the uneven workload")
@@ -69,6 +69,13 @@ def build_workload(name, n_media):
     elif name == "rodgauss512":
         media = [W.c2_medium(20)]
         desc = "rodgauss512: 512^2, h 0.1 mm, dt 20 ns, 4000 steps, 128 elements, 16 transmits, 2.5 MHz Ricker"
+    elif name == "ring188":
+        # the paper's acquisition: gradient at the water start model against rod data
+        media = [W.ring188(60, rods=False)]
+        desc = ("ring188: 188^2 over 10 cm (h 0.532 mm), dt 90.243 ns, 1034 steps, 16-element ring, "
+                "16 transmits, 3 receivers each, 350 kHz Gaussian-derivative pulse; water start model, "
+                "observed data from a water + rods phantom")
+        return media, [W.ring188(60, rods=True)], desc
     else:
         media = [W.c1_small()]
         desc = "disc128: 128^2, h 0.2 mm, dt 20 ns, 1000 steps, 32 elements, 1 transmit, 1 MHz Ricker"

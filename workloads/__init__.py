@@ -129,13 +129,14 @@ def array_geometry(nx, nz, nt, h, dt, n_el, pitch, n_tx=None, tx_elems=None,
 
 
 def ring_geometry(n: int, nt: int, h: float, dt: float, n_el: int = 16,
-                  radius_cells: Optional[float] = None, n_adj: int = 1) -> Geometry:
+                  radius_cells: Optional[float] = None, n_adj: int = 1, npml: int = NPML,
+                  cref: float = 1540.0) -> Geometry:
     """Elements on a ring (Sec. IV: 16 elements on a 10 cm ring); transmit p
     is received by the opposite element and its ``n_adj`` neighbours on
     each side (n_R = 3 for n_adj = 1)."""
     cx = cz = (n - 1) / 2.0
     if radius_cells is None:
-        radius_cells = (n - 1) / 2.0 - NPML - 2
+        radius_cells = (n - 1) / 2.0 - npml - 2
     ang = 2 * math.pi * np.arange(n_el) / n_el
     ix = np.rint(cx + radius_cells * np.cos(ang)).astype(np.int64)
     iz = np.rint(cz + radius_cells * np.sin(ang)).astype(np.int64)
@@ -145,7 +146,8 @@ def ring_geometry(n: int, nt: int, h: float, dt: float, n_el: int = 16,
     for p in range(n_el):
         opp = (p + n_el // 2) % n_el
         rcv.append([cells[(opp + k) % n_el] for k in range(-n_adj, n_adj + 1)])
-    return Geometry(nx=n, nz=n, nt=nt, h=h, dt=dt, src=src, rcv=np.asarray(rcv, np.int32))
+    return Geometry(nx=n, nz=n, nt=nt, h=h, dt=dt, src=src, rcv=np.asarray(rcv, np.int32), npml=npml,
+                    pml_cref=cref)
 
 
 # --------------------------------------------------------------------------
@@ -265,6 +267,51 @@ def partner_medium(m: Medium, seed: int) -> Medium:
     rng = np.random.default_rng(seed)
     c, rho = rod_gaussian_medium(rng, g.nx, g.nz, g.h, g.npml)
     return Medium(g, c, rho, m.wavelet, name=m.name + f"_obs{seed}")
+
+
+def phantom_rods(rng, n: int, h: float, ring_radius: float, n_rods=(1, 3), rod_radius: float = 5e-3,
+                 c_water: float = 1500.0, c_rod=(2700.0, 1588.0), gap: float = 1e-3):
+    """Water bath with 1-3 rods of 1 cm diameter, each at the bone or the
+    edema speed (Sec. VI phantom: 2700 and 1588 m/s in ~1500 m/s water),
+    centred inside the ring without overlapping; constant density 1000."""
+    c = np.full((n, n), c_water, np.float64)
+    X, Z = _grid_xy(n, n, h)
+    ctr = (n - 1) * h / 2
+    k = int(rng.integers(n_rods[0], n_rods[1] + 1))
+    reach = ring_radius - rod_radius - gap
+    placed = []
+    for _ in range(k):
+        for _attempt in range(200):
+            r = reach * math.sqrt(float(rng.random()))
+            a = 2 * math.pi * float(rng.random())
+            xc, zc = ctr + r * math.cos(a), ctr + r * math.sin(a)
+            if all((xc - x) ** 2 + (zc - z) ** 2 >= (2 * rod_radius + gap) ** 2 for x, z in placed):
+                break
+        else:
+            continue
+        placed.append((xc, zc))
+        c[(X - xc) ** 2 + (Z - zc) ** 2 <= rod_radius ** 2] = float(c_rod[int(rng.integers(0, len(c_rod)))])
+    return c.astype(np.float32), np.full((n, n), 1000.0, np.float32)
+
+
+def ring188(seed: int = 60, rods: bool = True, n: int = 188, nt: int = 1034) -> Medium:
+    """The paper's acquisition (Sec. IV-VI): a 10 cm square domain on a
+    188 x 188 grid (h = 0.1/188 m, about lambda/8 at 350 kHz in water),
+    dt = 90.243 ns, 1034 steps; 16 elements on a ring, each transmitting
+    once and received by the opposite element and its two neighbours
+    (n_R = 3); a 350 kHz Gaussian-derivative pulse; layer reference speed
+    1500 m/s (which gives the paper's D_max of 1.46e6).  ``rods`` draws the
+    water + rods phantom, else homogeneous water (the FWI start model).
+    ``n`` and ``nt`` shrink the case at the same physical size."""
+    h, dt = 0.1 / n, 90.243e-9 * 188 / n
+    geom = ring_geometry(n, nt, h, dt, n_el=16, n_adj=1, cref=1500.0)
+    ring_r = ((n - 1) / 2.0 - NPML - 2) * h
+    if rods:
+        c, rho = phantom_rods(np.random.default_rng(seed), n, h, ring_r)
+    else:
+        c, rho = np.full((n, n), 1500.0, np.float32), np.full((n, n), 1000.0, np.float32)
+    w = np.tile(gaussian_derivative(350e3, dt, nt)[None, :], (16, 1))
+    return Medium(geom, c, rho, w, name=f"ring{n}_{'rods' if rods else 'water'}_s{seed}")
 
 
 def small_random_medium(seed: int, nx: int, nz: int, nt: int, n_tx: int = 2,
