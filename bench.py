@@ -40,7 +40,7 @@ def parse():
     ap.add_argument("--workload", default="uneven64", choices=["uneven64", "rodgauss512", "disc128", "ring188", "unfold16"])
     ap.add_argument("--unfold-k", type=int, default=8, help="unfolded iterations (unfold16)")
     ap.add_argument("--unfold-backprop", default="fd", choices=["none", "fd"])
-    ap.add_argument("--media", type=int, default=64, help="media of the uneven workload")
+    ap.add_argument("--media", type=int, default=64, help="media of the uneven workload (ring188: phantoms, default 1)")
     ap.add_argument("--nt", type=int, default=0, help="override every medium's step count (counter runs)")
     ap.add_argument("--mode", default="batched", choices=["batched", "plain"])
     ap.add_argument("--group", type=int, default=0)
@@ -71,11 +71,12 @@ def build_workload(name, n_media):
         desc = "rodgauss512: 512^2, h 0.1 mm, dt 20 ns, 4000 steps, 128 elements, 16 transmits, 2.5 MHz Ricker"
     elif name == "ring188":
         # the paper's acquisition: gradient at the water start model against rod data
-        media = [W.ring188(60, rods=False)]
-        desc = ("ring188: 188^2 over 10 cm (h 0.532 mm), dt 90.243 ns, 1034 steps, 16-element ring, "
+        k = n_media if n_media != 64 else 1
+        media = [W.ring188(60 + i, rods=False) for i in range(k)]
+        desc = (f"ring188 x{k}: 188^2 over 10 cm (h 0.532 mm), dt 90.243 ns, 1034 steps, 16-element ring, "
                 "16 transmits, 3 receivers each, 350 kHz Gaussian-derivative pulse; water start model, "
-                "observed data from a water + rods phantom")
-        return media, [W.ring188(60, rods=True)], desc
+                "observed data from water + rods phantoms")
+        return media, [W.ring188(60 + i, rods=True) for i in range(k)], desc
     else:
         media = [W.c1_small()]
         desc = "disc128: 128^2, h 0.2 mm, dt 20 ns, 1000 steps, 32 elements, 1 transmit, 1 MHz Ricker"
