@@ -250,6 +250,8 @@ def main():
         tuned = F.autotune(grids, dtype=dtype, mode=args.mode, group=args.group, cache=args.tune_cache or None)
         tuned["seconds"] = round(time.perf_counter() - t0, 2)
         args.rows, args.spl = tuned["rows"], tuned["steps_per_launch"]
+        if args.group == 0:
+            args.group = tuned["group"]
         progress(f"autotuned: {tuned}")
     plan = make_plan(media, dtype, args.mode, args, c_max)
     info = plan.info

@@ -171,11 +171,12 @@ fwi_status fwi_plan_check(fwi_plan *plan);
 
 void fwi_plan_destroy(fwi_plan *plan);
 
-/* Autotuner: pick steps_per_launch and rows for these grids by timing short
- * device probes of every feasible candidate (the grids' schedules cut to 24
- * steps, every plane kept, a homogeneous medium) and keeping the fastest per
+/* Autotuner: pick steps_per_launch, rows and (when base->group is 0, for
+ * FWI_BATCHED) group for these grids by timing short device probes of every
+ * feasible candidate (the grids' schedules cut to 24 steps, every plane kept,
+ * a homogeneous medium; groups 4, 2 and 1) and keeping the fastest per
  * cell-update.  *out receives *base (or the defaults when base is NULL)
- * with those two fields set; *ns_per_update (optional) the probe's time.
+ * with those fields set; *ns_per_update (optional) the probe's time.
  * When base->tune_cache names a file, a cached choice for the same GPU
  * architecture, dtype, mode, group and size class is reused and new choices
  * are stored there (small JSON object).  Allocates and frees its own device

@@ -195,7 +195,8 @@ def _grid_array(grids, keep):
 def autotune(grids: Sequence[GridSpec], dtype: str = "f32", mode: str = "batched", group: int = 0,
              cache: Optional[str] = None) -> dict:
     """Time short device probes of the kernel variants for these grids and
-    return the fastest ``steps_per_launch`` and ``rows`` (fwi_autotune)."""
+    return the fastest ``steps_per_launch``, ``rows`` and (``group`` = 0)
+    ``group`` (fwi_autotune)."""
     lib = _lib()
     keep = []
     arr = _grid_array(list(grids), keep)
@@ -210,7 +211,8 @@ def autotune(grids: Sequence[GridSpec], dtype: str = "f32", mode: str = "batched
     st = lib.fwi_autotune(dt, arr, len(grids), C.byref(base), C.byref(out), C.byref(ns))
     if st != _abi.FWI_OK:
         raise FwiError(st, lib.fwi_last_create_error().decode())
-    return {"steps_per_launch": out.steps_per_launch, "rows": out.rows, "ns_per_update": ns.value}
+    return {"steps_per_launch": out.steps_per_launch, "rows": out.rows, "group": out.group,
+            "ns_per_update": ns.value}
 
 
 def _torch_dtype(dtype):

@@ -1125,34 +1125,39 @@ extern "C" fwi_status fwi_plan_check(fwi_plan* p)
 // homogeneous medium at 80% of c_max, zero wavelets and observed traces
 // (the kernels' cost does not depend on the values).  Each feasible
 // candidate runs one warm-up gradient and two timed ones; the fastest per
-// cell-update wins.  Results are cached in a small JSON file keyed by the
-// GPU architecture, dtype, mode, group and the grids' size class.
+// cell-update wins.  Unless the caller fixes it, the group (transmits per
+// work item) is searched too.  Results are cached in a small JSON file keyed
+// by the GPU architecture, dtype, mode, group and the grids' size class.
 
 namespace {
 
 struct TuneChoice {
-    int S = 0, rows = 0;
+    int S = 0, rows = 0, group = 0;
     double ns = 0;
 };
 
+// G = 0: the group is part of the search (the size class counts transmits).
 std::string tune_key(const char* arch, fwi_dtype dtype, const fwi_options& o, int G, const fwi_grid* grids, int n)
 {
     double cells = 0;
     int items = 0;
     for (int i = 0; i < n; ++i) {
         cells += (double)grids[i].nx * grids[i].nz;
-        items += (grids[i].n_tx + G - 1) / G;
+        items += G ? (grids[i].n_tx + G - 1) / G : grids[i].n_tx;
     }
     char buf[256];
     std::string a(arch);
     a = a.substr(0, a.find(':'));
-    std::snprintf(buf, sizeof buf, "%s|%s|%s|G%d|c%ld|i%ld", a.c_str(), dtype == FWI_F64 ? "f64" : "f32",
-                  o.mode == FWI_PLAIN ? "plain" : "batched", G, std::lround(std::log2(cells / n)),
+    char gs[16];
+    if (G) std::snprintf(gs, sizeof gs, "G%d", G);
+    else std::snprintf(gs, sizeof gs, "Gauto");
+    std::snprintf(buf, sizeof buf, "%s|%s|%s|%s|c%ld|i%ld", a.c_str(), dtype == FWI_F64 ? "f64" : "f32",
+                  o.mode == FWI_PLAIN ? "plain" : "batched", gs, std::lround(std::log2(cells / n)),
                   std::lround(std::log2((double)items)));
     return buf;
 }
 
-// Entries are lines  "key": {"steps_per_launch": S, "rows": R, "ns_per_update": X}
+// Entries are lines  "key": {"steps_per_launch": S, "rows": R, "group": G, "ns_per_update": X}
 bool cache_read(const char* path, std::vector<std::pair<std::string, TuneChoice>>& ent)
 {
     FILE* f = std::fopen(path, "r");
@@ -1166,10 +1171,12 @@ bool cache_read(const char* path, std::vector<std::pair<std::string, TuneChoice>
         TuneChoice c;
         const char* sp = std::strstr(q1, "\"steps_per_launch\":");
         const char* rw = std::strstr(q1, "\"rows\":");
+        const char* gp = std::strstr(q1, "\"group\":");
         const char* ns = std::strstr(q1, "\"ns_per_update\":");
-        if (!sp || !rw || !ns) continue;
+        if (!sp || !rw || !gp || !ns) continue;
         c.S = std::atoi(sp + 19);
         c.rows = std::atoi(rw + 7);
+        c.group = std::atoi(gp + 8);
         c.ns = std::atof(ns + 16);
         ent.emplace_back(std::string(q0 + 1, q1), c);
     }
@@ -1184,9 +1191,9 @@ void cache_write(const char* path, const std::vector<std::pair<std::string, Tune
     if (!f) return;
     std::fprintf(f, "{\n");
     for (size_t i = 0; i < ent.size(); ++i)
-        std::fprintf(f, "\"%s\": {\"steps_per_launch\": %d, \"rows\": %d, \"ns_per_update\": %.6g}%s\n",
-                     ent[i].first.c_str(), ent[i].second.S, ent[i].second.rows, ent[i].second.ns,
-                     i + 1 < ent.size() ? "," : "");
+        std::fprintf(f, "\"%s\": {\"steps_per_launch\": %d, \"rows\": %d, \"group\": %d, \"ns_per_update\": %.6g}%s\n",
+                     ent[i].first.c_str(), ent[i].second.S, ent[i].second.rows, ent[i].second.group,
+                     ent[i].second.ns, i + 1 < ent.size() ? "," : "");
     std::fprintf(f, "}\n");
     std::fclose(f);
     std::rename(tmp.c_str(), path);
@@ -1229,7 +1236,8 @@ extern "C" fwi_status fwi_autotune(fwi_dtype dtype, const fwi_grid* grids, int32
         fwi_status st = validate_grid(grids[i], i, msg);
         if (st != FWI_OK) { g_create_error = msg; return st; }
     }
-    const int G = o.group ? o.group : (o.mode == FWI_PLAIN ? 1 : 4);
+    // transmits per work item: the caller's, else searched over 4, 2, 1 (plain: 1)
+    const int G = o.group ? o.group : (o.mode == FWI_PLAIN ? 1 : 0);
     int dev = 0;
     hipDeviceProp_t prop;
     if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) {
@@ -1240,10 +1248,11 @@ extern "C" fwi_status fwi_autotune(fwi_dtype dtype, const fwi_grid* grids, int32
     std::vector<std::pair<std::string, TuneChoice>> cache;
     if (o.tune_cache && cache_read(o.tune_cache, cache))
         for (auto& e : cache)
-            if (e.first == key && e.second.S > 0) {
+            if (e.first == key && e.second.S > 0 && e.second.group > 0) {
                 *out = o;
                 out->steps_per_launch = e.second.S;
                 out->rows = e.second.rows;
+                out->group = e.second.group;
                 if (ns_per_update) *ns_per_update = e.second.ns;
                 return FWI_OK;
             }
@@ -1289,9 +1298,14 @@ extern "C" fwi_status fwi_autotune(fwi_dtype dtype, const fwi_grid* grids, int32
         hipEvent_t e0, e1;
         (void)hipEventCreate(&e0);
         (void)hipEventCreate(&e1);
+        const int groups_auto[] = {4, 2, 1};
+        const int n_groups = G ? 1 : 3;
+        for (int gi = 0; gi < n_groups; ++gi)
         for (auto& cd : cands) {
+            const int grp = G ? G : groups_auto[gi];
             if (o.mode == FWI_PLAIN && cd[0] == 2) continue;
             fwi_options po = o;
+            po.group = grp;
             po.steps_per_launch = cd[0];
             po.rows = cd[1];
             po.ckpt_interval = 1 << 30;
@@ -1313,7 +1327,7 @@ extern "C" fwi_status fwi_autotune(fwi_dtype dtype, const fwi_grid* grids, int32
             float ms = 0;
             if (good && hipEventElapsedTime(&ms, e0, e1) == hipSuccess) {
                 const double ns = ms * 1e6 / (2.0 * (double)plan->cell_updates);
-                if (best.S == 0 || ns < best.ns) best = TuneChoice{cd[0], cd[1], ns};
+                if (best.S == 0 || ns < best.ns) best = TuneChoice{cd[0], cd[1], grp, ns};
             }
             (void)hipStreamSynchronize(st);
             (void)hipFree(ws);
@@ -1338,6 +1352,7 @@ extern "C" fwi_status fwi_autotune(fwi_dtype dtype, const fwi_grid* grids, int32
     *out = o;
     out->steps_per_launch = best.S;
     out->rows = best.rows;
+    out->group = best.group;
     if (ns_per_update) *ns_per_update = best.ns;
     return FWI_OK;
 }

@@ -269,8 +269,9 @@ def test_persistent_barrier_limit_reports_error():
 
 
 def test_autotune_choice_and_cache(tmp_path):
-    """The autotuner returns a feasible (steps per launch, rows) pair, writes
-    it to its JSON cache and reuses it; a plan built with it passes parity."""
+    """The autotuner returns a feasible (steps per launch, rows, group), writes
+    it to its JSON cache and reuses it, keeps a group the caller fixes; a plan
+    built with its choice passes parity."""
     import json
     import paper_2603_04070_amd as F
     media, obs = _two_media()
@@ -278,12 +279,16 @@ def test_autotune_choice_and_cache(tmp_path):
     cache = str(tmp_path / "tune.json")
     a = F.autotune(grids, dtype="f32", cache=cache)
     assert (a["steps_per_launch"], a["rows"]) in {(2, 1), (2, 2), (2, 4), (1, 2), (1, 4), (1, 8)}
+    assert a["group"] in (1, 2, 4)
     assert a["ns_per_update"] > 0
     entries = json.load(open(cache))
-    assert len(entries) == 1
+    assert len(entries) == 1 and list(entries.values())[0]["group"] == a["group"]
     b = F.autotune(grids, dtype="f32", cache=cache)
-    assert (b["steps_per_launch"], b["rows"], b["ns_per_update"]) == (a["steps_per_launch"], a["rows"],
-                                                                     pytest.approx(a["ns_per_update"], rel=1e-5))
-    res, plan = gpu_run(media, obs, dtype="f32", ckpt=7, steps_per_launch=a["steps_per_launch"], rows=a["rows"])
+    assert (b["steps_per_launch"], b["rows"], b["group"], b["ns_per_update"]) == (
+        a["steps_per_launch"], a["rows"], a["group"], pytest.approx(a["ns_per_update"], rel=1e-5))
+    fixed = F.autotune(grids, dtype="f32", group=2)
+    assert fixed["group"] == 2
+    res, plan = gpu_run(media, obs, dtype="f32", ckpt=7, steps_per_launch=a["steps_per_launch"], rows=a["rows"],
+                        group=a["group"])
     for r, m, o in zip(res, media, obs):
         _check(r, oracle_grad(m, o), "f32")
