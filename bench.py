@@ -189,6 +189,7 @@ def run_unfold(args):
         loss.backward()
         torch.cuda.synchronize()
         t2 = time.perf_counter()
+        progress(f"unfold iteration {it}: forward {t1 - t0:.1f} s, backward {t2 - t1:.1f} s")
         if it >= args.warmup:
             times.append((t1 - t0, t2 - t1))
     fw = float(np.mean([a for a, _ in times]))
@@ -345,11 +346,12 @@ def run_cpu_baseline(media, args):
     m = media[0]
     g = m.geom
     threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or (os.cpu_count() or 1)
-    ntx = min(2, g.n_tx)
+    # ~15 s at the oracle's measured ~0.0175 G updates/s per thread: as many
+    # transmits as the full schedule allows, else the first steps of two
+    budget_updates = 15.0 * 0.0175e9 * min(threads, 16)
+    ntx = int(min(g.n_tx, max(2, budget_updates // (2 * g.nx * g.nz * g.nt))))
     steps = args.cpu_steps
     if steps <= 0:
-        # ~15 s at an assumed ~0.15 G updates/s per thread of the oracle, at most the full schedule
-        budget_updates = 15.0 * 0.15e9 * min(threads, 16)
         steps = int(max(50, min(g.nt, budget_updates / (2 * g.nx * g.nz * ntx))))
     import copy
     gs = copy.copy(g)

@@ -10,7 +10,8 @@ so the direction carries the sign here.)
 
 Every misfit and gradient is one batched library call over all media of the
 problem: ``fwi_plan_execute`` for (J, dJ/dc) and a forward-only plan for the
-line-search misfits.  Density is held fixed (the paper inverts SoS only).
+line-search misfits.  The paper inverts SoS only, with density held fixed;
+density alone, or both together, can be inverted from the same calls.
 
 The optimiser itself (:func:`minimize`) only sees callables returning J and
 dJ/dx for a list of tensors, one per medium, so it runs unchanged on any
@@ -54,7 +55,7 @@ def lbfgs_direction(g: torch.Tensor, S: Sequence[torch.Tensor], Y: Sequence[torc
 def minimize(fg: Callable[[List[torch.Tensor]], Tuple[List[float], List[torch.Tensor]]],
              f: Callable[[List[torch.Tensor]], List[float]],
              x0: Sequence[torch.Tensor], iters: int, method: str = "lbfgs", memory: int = 5,
-             step: float = 10.0, lo: Optional[float] = None, hi: Optional[float] = None,
+             step: float = 10.0, lo=None, hi=None,
              armijo: float = 1e-4, backtracks: int = 10):
     """Minimise independent objectives J_i(x_i) for a batch of tensors x_i.
 
@@ -63,7 +64,7 @@ def minimize(fg: Callable[[List[torch.Tensor]], Tuple[List[float], List[torch.Te
     "descent".  The first step of a medium (and any step after its L-BFGS
     memory was reset) is scaled so that its largest entry is ``step``; later
     L-BFGS steps start from the unit step.  Iterates are projected onto
-    [lo, hi]; variables held at a bound by the gradient are left out of the
+    [lo, hi] (scalars, or tensors broadcastable to each x_i); variables held at a bound by the gradient are left out of the
     direction (a projected method with an active set, enough for bounds that
     only guard the stability limit).  A trial is accepted when J_t <= J + armijo * gamma * g.d,
     else gamma is halved, at most ``backtracks`` times (then the medium keeps
@@ -167,21 +168,27 @@ class FWI:
         dev = c[0].device
         ios = []
         for g, ci, ri, wi, oi in zip(self.grids, c, rho, wavelet, d_obs):
-            io = {"c": ci.contiguous(), "rho": ri, "wavelet": wi, "d_obs": oi,
+            io = {"c": ci.contiguous(), "rho": ri.contiguous(), "wavelet": wi, "d_obs": oi,
                   "traces": torch.empty((g.n_tx, g.nt, g.n_rcv), dtype=td, device=dev),
                   "misfit": torch.zeros(1, dtype=torch.float64, device=dev)}
             if grad:
                 io["grad_c"] = torch.empty((g.nz, g.nx), dtype=td, device=dev)
+                io["grad_rho"] = torch.empty((g.nz, g.nx), dtype=td, device=dev)
             ios.append(io)
         return ios
 
-    def misfit_and_gradient(self, c, rho, wavelet, d_obs):
-        """([J_i], [dJ_i/dc_i]) for every medium: one library call."""
+    def misfit_and_gradients(self, c, rho, wavelet, d_obs):
+        """([J_i], [dJ_i/dc_i], [dJ_i/drho_i]) for every medium: one library call."""
         ios = self._ios(c, rho, wavelet, d_obs, grad=True)
         self.grad_plan.execute(ios, self._workspace(self.grad_plan, c[0].device))
         self.grad_plan.check()
         self.calls["gradient"] += 1
-        return [float(io["misfit"]) for io in ios], [io["grad_c"] for io in ios]
+        return [float(io["misfit"]) for io in ios], [io["grad_c"] for io in ios], [io["grad_rho"] for io in ios]
+
+    def misfit_and_gradient(self, c, rho, wavelet, d_obs):
+        """([J_i], [dJ_i/dc_i]) for every medium: one library call."""
+        J, gc, _ = self.misfit_and_gradients(c, rho, wavelet, d_obs)
+        return J, gc
 
     def misfit(self, c, rho, wavelet, d_obs):
         """[J_i] for every medium: one forward-only library call."""
@@ -192,11 +199,41 @@ class FWI:
         return [float(io["misfit"]) for io in ios]
 
     def run(self, c0, rho, wavelet, d_obs, iters: int = 10, method: str = "lbfgs", memory: int = 5,
-            step: float = 10.0):
-        """Invert c from the start models ``c0`` (list of [nz, nx] device
-        tensors) with rho, wavelets and observed traces fixed; returns
-        (c list, misfit history)."""
+            step: float = 10.0, param: str = "c", rho_bounds=(500.0, 3000.0)):
+        """Invert from the start models (lists of [nz, nx] device tensors)
+        with the wavelets and observed traces fixed.  ``param``: "c" (SoS,
+        rho held fixed, as in the paper), "rho" (density, c held fixed) or
+        "both" (c and rho together, each with its own bounds).  Returns
+        (c list, rho list, misfit history)."""
         lo, hi = self.c_bounds
-        return minimize(lambda xs: self.misfit_and_gradient(xs, rho, wavelet, d_obs),
-                        lambda xs: self.misfit(xs, rho, wavelet, d_obs),
-                        c0, iters, method=method, memory=memory, step=step, lo=lo, hi=hi)
+        if param == "c":
+            xs, hist = minimize(lambda xs: self.misfit_and_gradient(xs, rho, wavelet, d_obs),
+                                lambda xs: self.misfit(xs, rho, wavelet, d_obs),
+                                c0, iters, method=method, memory=memory, step=step, lo=lo, hi=hi)
+            return xs, [r.clone() for r in rho], hist
+        if param == "rho":
+            fg = lambda xs: (lambda J, gc, gr: (J, gr))(*self.misfit_and_gradients(c0, xs, wavelet, d_obs))
+            xs, hist = minimize(fg, lambda xs: self.misfit(c0, xs, wavelet, d_obs), rho, iters, method=method,
+                                memory=memory, step=step, lo=rho_bounds[0], hi=rho_bounds[1])
+            return [c.clone() for c in c0], xs, hist
+        if param != "both":
+            raise ValueError("param must be 'c', 'rho' or 'both'")
+
+        def split(xs):
+            return [x[0] for x in xs], [x[1] for x in xs]
+
+        def fg(xs):
+            c, r = split(xs)
+            J, gc, gr = self.misfit_and_gradients(c, r, wavelet, d_obs)
+            return J, [torch.stack([a, b]) for a, b in zip(gc, gr)]
+
+        def f(xs):
+            return self.misfit(*split(xs), wavelet, d_obs)
+
+        dev, td = c0[0].device, c0[0].dtype
+        lo_t = torch.tensor([lo, rho_bounds[0]], dtype=td, device=dev).view(2, 1, 1)
+        hi_t = torch.tensor([hi, rho_bounds[1]], dtype=td, device=dev).view(2, 1, 1)
+        x0 = [torch.stack([c, r]) for c, r in zip(c0, rho)]
+        xs, hist = minimize(fg, f, x0, iters, method=method, memory=memory, step=step, lo=lo_t, hi=hi_t)
+        c, r = split(xs)
+        return [x.contiguous() for x in c], [x.contiguous() for x in r], hist

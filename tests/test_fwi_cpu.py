@@ -70,3 +70,14 @@ def test_minimize_respects_bounds():
     assert float(xs[0].min()) >= lo and float(xs[0].max()) <= hi
     # the bound-constrained minimiser of a separable quadratic is the clamp
     assert torch.allclose(xs[0], X[0].clamp(lo, hi), atol=0.5)
+
+
+def test_minimize_per_channel_bounds():
+    """Tensor bounds broadcast per channel (the joint c / rho inversion)."""
+    f, fg, X = _quadratic(5, [(2, 5, 5)], cond=10.0)
+    lo = torch.tensor([1500.0, 1520.0], dtype=torch.float64).view(2, 1, 1)
+    hi = torch.tensor([1600.0, 1560.0], dtype=torch.float64).view(2, 1, 1)
+    x0 = [torch.full_like(X[0], 1540.0)]
+    xs, hist = minimize(fg, f, x0, 60, method="lbfgs", step=20.0, lo=lo, hi=hi)
+    assert torch.all(xs[0] >= lo) and torch.all(xs[0] <= hi)
+    assert torch.allclose(xs[0], torch.max(torch.min(X[0], hi), lo), atol=0.5)
