@@ -52,6 +52,7 @@ class _Medium(C.Structure):
         ("grad_wavelet", C.c_void_p),
         ("misfit", C.c_void_p),
         ("fields", C.c_void_p),
+        ("order", C.c_int32), ("pad", C.c_int32),
     ]
 
 
@@ -69,6 +70,8 @@ def _load():
         lib.om_dmax.restype = C.c_double
         lib.om_damping.argtypes = [C.c_int, C.c_int, C.c_int, C.c_double, C.c_void_p]
         lib.om_damping.restype = None
+        lib.om_apply_lb.argtypes = [C.POINTER(_Medium), C.c_void_p, C.c_void_p]
+        lib.om_apply_lb.restype = C.c_int
         _lib = lib
     return _lib
 
@@ -108,6 +111,7 @@ def _medium_struct(geom, c, rho, wavelet, keep):
     m.n_tx, m.n_rcv = geom.n_tx, geom.n_rcv
     m.src, m.rcv = _ptr(src), _ptr(rcv)
     m.wavelet, m.wavelet_stride = _ptr(w), stride
+    m.order = int(getattr(geom, "order", 2))
     return m
 
 
@@ -148,6 +152,26 @@ def run(geom, c, rho, wavelet, d_obs=None, d_adj=None, gradient: Optional[bool] 
         raise RuntimeError(f"oracle om_run failed with status {rc}")
     if "misfit" in out:
         out["misfit"] = float(out["misfit"][0])
+    return out
+
+
+def apply_lb(c, rho, h: float, v, order: int = 2) -> np.ndarray:
+    """L_b v on a grid of c.shape (test-only: u = 0 outside, b repeated)."""
+    nz, nx = np.shape(c)
+    keep = []
+
+    class _G:
+        pass
+    g = _G()
+    g.nx, g.nz, g.nt, g.npml, g.h, g.dt, g.pml_r, g.pml_cref = nx, nz, 1, 1, h, 1e-9, 0.1, 1500.0
+    g.src, g.rcv, g.order = np.zeros(1, np.int32), np.zeros((1, 1), np.int32), order
+    g.n_tx, g.n_rcv = 1, 1
+    m = _medium_struct(g, c, rho, np.zeros((1, 1)), keep)
+    v = _f64(v)
+    out = np.zeros((nz, nx))
+    rc = _load().om_apply_lb(C.byref(m), _ptr(v), _ptr(out))
+    if rc != 0:
+        raise RuntimeError(f"oracle om_apply_lb failed with status {rc}")
     return out
 
 

@@ -38,6 +38,16 @@
  *    dJ/dw_p[n] = lam^{n+1}[src_p].
  *  Output: g_c = 2 rho c g_kappa, g_rho = c^2 g_kappa - b^2 g_b, summed over transmits.
  *
+ * Fourth-order variant (order = 4).  Along each axis, the face flux between
+ *    cells j and j+1 is F = b_f (9/8 (u_{j+1} - u_j) - 1/24 (u_{j+2} - u_{j-1}))
+ *    with b_f = (b_j + b_{j+1})/2, and (L_b u)_i = h^-2 sum over both axes of
+ *    9/8 (F_{i+1/2} - F_{i-1/2}) - 1/24 (F_{i+3/2} - F_{i-3/2})  (staggered
+ *    fourth-order differences, so L_b = -h^-2 D^T B D stays symmetric).  Outside
+ *    the grid u = 0 and b repeats the nearest cell of that row or column, which
+ *    for order 2 is the border rule above.  The imaging term of a face becomes
+ *    G_f = -h^-2 (D u)_f (D w)_f, shared half and half by the cells whose b
+ *    make up b_f (ghost cells counting as the cell they repeat).
+ *
  * Replay of u^{t-1} in reverse order: every u^t is kept (store-all), or
  * (u^{jK}, u^{jK-1}) pairs are kept every K steps and each segment is
  * recomputed with the same step routine (bitwise identical to store-all).
@@ -67,6 +77,8 @@ typedef struct {
     double *grad_wavelet;           /* out [n_tx][nt] or NULL */
     double *misfit;                 /* out scalar or NULL */
     double *fields;                 /* out: forward fields u^1..u^T of transmit 0, [nt][nz*nx], or NULL */
+    int32_t order;                  /* spatial order of L_b: 2 (default when 0) or 4 */
+    int32_t pad;
 } om_medium;
 
 enum { OM_OK = 0, OM_ERR_INVALID = 1, OM_ERR_NOMEM = 4 };
@@ -101,6 +113,7 @@ void om_damping(int nx, int nz, int N, double dmax, double *D)
 
 typedef struct {
     int nx, nz;
+    int order;                      /* 2 or 4 */
     int nthr;                       /* OpenMP threads of the row loops */
     double ih2;                     /* h^-2 */
     double *a, *beta, *gam, *kap, *b, *gk;   /* gk = gamma * kappa */
@@ -115,6 +128,7 @@ static int coef_make(const om_medium *m, om_coef *k)
 {
     int n = m->nx * m->nz;
     k->nx = m->nx; k->nz = m->nz;
+    k->order = m->order == 4 ? 4 : 2;
     k->ih2 = 1.0 / (m->h * m->h);
     k->a = malloc(sizeof(double) * n); k->beta = malloc(sizeof(double) * n);
     k->gam = malloc(sizeof(double) * n); k->kap = malloc(sizeof(double) * n);
@@ -154,9 +168,59 @@ static double face_b(const om_coef *k, int x, int xn)
     return xn < 0 ? k->b[x] : 0.5 * (k->b[x] + k->b[xn]);
 }
 
+/* ---- fourth order: faces along one axis of a row (axis 0) or column (axis 1) */
+
+/* v at position i along the axis through (ix, iz); 0 outside the grid */
+static double val_ax(const om_coef *k, const double *v, int ix, int iz, int axis, int i)
+{
+    int n = axis == 0 ? k->nx : k->nz;
+    if (i < 0 || i >= n) return 0.0;
+    return axis == 0 ? v[iz * k->nx + i] : v[i * k->nx + ix];
+}
+
+/* cell index of position i along the axis, clamped to the grid (b repeats outward) */
+static int cell_ax(const om_coef *k, int ix, int iz, int axis, int i)
+{
+    int n = axis == 0 ? k->nx : k->nz;
+    if (i < 0) i = 0;
+    if (i > n - 1) i = n - 1;
+    return axis == 0 ? iz * k->nx + i : i * k->nx + ix;
+}
+
+/* (D v) at the face between positions j and j+1 along the axis */
+static double d4_face(const om_coef *k, const double *v, int ix, int iz, int axis, int j)
+{
+    return 9.0 / 8.0 * (val_ax(k, v, ix, iz, axis, j + 1) - val_ax(k, v, ix, iz, axis, j))
+         - 1.0 / 24.0 * (val_ax(k, v, ix, iz, axis, j + 2) - val_ax(k, v, ix, iz, axis, j - 1));
+}
+
+static double b4_face(const om_coef *k, int ix, int iz, int axis, int j)
+{
+    return 0.5 * (k->b[cell_ax(k, ix, iz, axis, j)] + k->b[cell_ax(k, ix, iz, axis, j + 1)]);
+}
+
+/* flux b_f (D v)_f at the face between j and j+1 */
+static double flux4(const om_coef *k, const double *v, int ix, int iz, int axis, int j)
+{
+    return b4_face(k, ix, iz, axis, j) * d4_face(k, v, ix, iz, axis, j);
+}
+
+static double lb4_at(const om_coef *k, const double *v, int ix, int iz)
+{
+    double s = 0.0;
+    for (int axis = 0; axis < 2; ++axis) {
+        int i = axis == 0 ? ix : iz;
+        s += 9.0 / 8.0 * (flux4(k, v, ix, iz, axis, i) - flux4(k, v, ix, iz, axis, i - 1))
+           - 1.0 / 24.0 * (flux4(k, v, ix, iz, axis, i + 1) - flux4(k, v, ix, iz, axis, i - 2));
+    }
+    return k->ih2 * s;
+}
+
 /* (L_b v)_x */
 static double lb_at(const om_coef *k, const double *v, int ix, int iz)
 {
+    if (k->order == 4) return lb4_at(k, v, ix, iz);
+
     int nb[4], x = iz * k->nx + ix;
     neighbours(k->nx, k->nz, ix, iz, nb);
     double s = 0.0;
@@ -193,12 +257,39 @@ static void adj_step(const om_coef *k, const double *l2, const double *l1, doubl
         }
 }
 
+/* Fourth-order imaging: g_kappa as below; every face of every row and column
+ * (those between positions -2 .. n along the axis carry non-zero D u) gives
+ * G_f = -h^-2 (D u)_f (D w)_f, half to each cell whose b enters b_f. */
+static void imaging4(const om_coef *k, const double *lam, const double *u, const double *w,
+                     double *gkap, double *gb)
+{
+    int nx = k->nx, nz = k->nz;
+    for (int iz = 0; iz < nz; ++iz)
+        for (int ix = 0; ix < nx; ++ix) {
+            int x = iz * nx + ix;
+            gkap[x] += k->gam[x] * lam[x] * lb_at(k, u, ix, iz);
+        }
+    for (int axis = 0; axis < 2; ++axis) {
+        int nl = axis == 0 ? nz : nx;          /* lines */
+        int n = axis == 0 ? nx : nz;           /* cells per line */
+        for (int l = 0; l < nl; ++l) {
+            int ix = axis == 0 ? 0 : l, iz = axis == 0 ? l : 0;
+            for (int j = -2; j <= n; ++j) {
+                double G = -k->ih2 * d4_face(k, u, ix, iz, axis, j) * d4_face(k, w, ix, iz, axis, j);
+                gb[cell_ax(k, ix, iz, axis, j)] += 0.5 * G;
+                gb[cell_ax(k, ix, iz, axis, j + 1)] += 0.5 * G;
+            }
+        }
+    }
+}
+
 /* Zero-lag cross-correlation of lam^t with u^{t-1}: adds to g_kappa, g_b. */
 static void imaging(const om_coef *k, const double *lam, const double *u, double *w,
                     double *gkap, double *gb, int par)
 {
     int nx = k->nx, nz = k->nz, n = nx * nz;
     for (int x = 0; x < n; ++x) w[x] = k->gk[x] * lam[x];
+    if (k->order == 4) { imaging4(k, lam, u, w, gkap, gb); return; }
 #pragma omp parallel for schedule(static) if (par) num_threads(k->nthr)
     for (int iz = 0; iz < nz; ++iz)
         for (int ix = 0; ix < nx; ++ix) {
@@ -346,6 +437,7 @@ static int valid(const om_medium *m)
     if (!(m->h > 0) || !(m->dt > 0) || !m->c || !m->rho || !m->src || !m->wavelet) return 0;
     if (m->n_rcv > 0 && !m->rcv) return 0;
     if (m->wavelet_stride != 0 && m->wavelet_stride < m->nt) return 0;
+    if (m->order != 0 && m->order != 2 && m->order != 4) return 0;
     int n = m->nx * m->nz;
     for (int p = 0; p < m->n_tx; ++p) {
         if (m->src[p] < 0 || m->src[p] >= n) return 0;
@@ -456,6 +548,18 @@ int om_born(om_medium *m, const double *dc, const double *drho, double *dtraces)
     }
     for (int i = 0; i < 3; ++i) { free(u[i]); free(du[i]); }
     free(dkap); free(db);
+    coef_free(&k);
+    return OM_OK;
+}
+
+/* out = L_b v on the grid of m (test-only: the operator's order of accuracy). */
+int om_apply_lb(const om_medium *m, const double *v, double *out)
+{
+    if (!m || m->nx < 1 || m->nz < 1 || !m->rho || !m->c || !v || !out) return OM_ERR_INVALID;
+    om_coef k;
+    if (coef_make(m, &k) != OM_OK) return OM_ERR_NOMEM;
+    for (int iz = 0; iz < m->nz; ++iz)
+        for (int ix = 0; ix < m->nx; ++ix) out[iz * m->nx + ix] = lb_at(&k, v, ix, iz);
     coef_free(&k);
     return OM_OK;
 }

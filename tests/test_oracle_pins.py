@@ -20,6 +20,10 @@ Each test names what it pins:
   P13 checkpointed replay is bitwise store-all
   P14 stability bound: growth above it, bounded below
   P15 absorbing-layer efficacy (reflection below -40 dB)
+  P16 fourth-order operator: its order of accuracy against closed-form
+      Laplacians (constant and variable density)
+  P17 fourth-order variant: Green's function, dot products, brute-force
+      gradient, density-scale invariance, checkpoint replay, stability bound
 """
 import json
 import math
@@ -349,3 +353,163 @@ def test_p15_absorbing_layer_efficacy():
     print("reflection dB (layer, no damping)", db)
     assert db[1e-3] < -30.0
     assert db[1e-3] < db[1 - 1e-12] - 25.0
+
+
+# ------------------------------------------------------------------ P16
+def _gauss_fields(n, L, var_b):
+    """u = exp(-r^2 / 2 s^2) centred on an n x n grid of side L (zero to
+    round-off at the border), b = 1/rho constant or smooth; returns h, u, rho
+    and the closed form of div(b grad u)."""
+    h = L / (n - 1)
+    x = np.arange(n) * h - L / 2
+    X, Z = np.meshgrid(x, x)
+    s = L / 12
+    u = np.exp(-(X ** 2 + Z ** 2) / (2 * s * s))
+    ux, uz = -X / s ** 2 * u, -Z / s ** 2 * u
+    lap = ((X ** 2 + Z ** 2) / s ** 4 - 2 / s ** 2) * u
+    if var_b:
+        k = 2 * math.pi / L
+        rho = 1000.0 * (1 + 0.2 * np.sin(k * X + 0.3) * np.cos(k * Z - 0.2))
+        drx = 1000.0 * 0.2 * k * np.cos(k * X + 0.3) * np.cos(k * Z - 0.2)
+        drz = -1000.0 * 0.2 * k * np.sin(k * X + 0.3) * np.sin(k * Z - 0.2)
+        b = 1 / rho
+        bx, bz = -drx / rho ** 2, -drz / rho ** 2
+    else:
+        rho = np.full_like(u, 1000.0)
+        b = 1 / rho
+        bx = bz = 0.0
+    return h, u, rho, b * lap + bx * ux + bz * uz
+
+
+@pytest.mark.parametrize("var_b", [False, True])
+def test_p16_operator_order_of_accuracy(var_b):
+    """Interior error of L_b u against div(b grad u) under h -> h/2 -> h/4:
+    order 2 for the second-order operator; order 4 for the fourth-order one
+    with constant density.  With variable density the face buoyancy's
+    arithmetic mean is second order, so the fourth-order operator's error
+    drifts from rate 4 towards 2, but stays over ten times below the
+    second-order operator's."""
+    L = 0.02
+    errs = {2: [], 4: []}
+    for n in (41, 81, 161):
+        h, u, rho, ref = _gauss_fields(n, L, var_b)
+        c = np.full_like(u, 1500.0)
+        m = slice(n // 4, 3 * n // 4)
+        for order in (2, 4):
+            out = O.apply_lb(c, rho, h, u, order)
+            errs[order].append(np.max(np.abs(out[m, m] - ref[m, m])) / np.max(np.abs(ref)))
+    rates = {o: [math.log2(e[i] / e[i + 1]) for i in range(2)] for o, e in errs.items()}
+    print("errors", errs, "rates", rates)
+    for r in rates[2]:
+        assert 1.9 <= r <= 2.1
+    if var_b:
+        assert all(e4 <= 0.1 * e2 for e4, e2 in zip(errs[4], errs[2]))
+    else:
+        for r in rates[4]:
+            assert 3.8 <= r <= 4.2
+        assert errs[4][-1] < 0.01 * errs[2][-1]
+
+
+def _order4(m):
+    m.geom.order = 4
+    return m
+
+
+def test_p17_green_function_fourth_order():
+    """Against the analytic 2-D response, the fourth-order variant is over
+    six times more accurate than the second-order operator at the same
+    (h, dt) on two grid levels (its spatial error is the smaller part; the
+    time stepping stays second order), and within 2 % at the finer level."""
+    c, f0 = 1500.0, 1e6
+    r_phys, half = 4.5e-3, 9e-3
+    wf = lambda t: (1 - 2 * (math.pi * f0 * (t - 1.5 / f0)) ** 2) * np.exp(-(math.pi * f0 * (t - 1.5 / f0)) ** 2)
+    errs = {2: [], 4: []}
+    for lev in range(2):
+        h = 0.1e-3 / 2 ** lev
+        dt = 0.3 * h / c
+        nt = int(round(6.2e-6 / dt))
+        ni = int(round(half / h))
+        n = 2 * ni + 1 + 2 * 20
+        cen = n // 2
+        off = int(round(r_phys / h))
+        g, ca, ra, w = _homog(n, nt, h, dt, c=c, src=[cen * n + cen], rcv=[[cen * n + cen + off]], f0=f0)
+        ana = O.green2d_trace(wf, r_phys, c, h, dt, nt)
+        for order in (2, 4):
+            g.order = order
+            errs[order].append(rel_l2(O.run(g, ca, ra, w, ckpt=2)["traces"][0, :, 0], ana))
+    print("errors", errs)
+    assert errs[4][-1] <= 2e-2
+    assert all(e4 * 6 <= e2 for e4, e2 in zip(errs[4], errs[2]))
+
+
+def test_p17_dot_products_fourth_order():
+    m = _order4(W.small_random_medium(5, 23, 19, 90, n_tx=3, n_rcv=5, npml=3, dup_receiver=True))
+    g = m.geom
+    rng = np.random.default_rng(1)
+    w = rng.standard_normal((g.n_tx, g.nt))
+    y = rng.standard_normal((g.n_tx, g.nt, g.n_rcv))
+    Fw = O.run(g, m.c, m.rho, w)["traces"]
+    Fty = O.run(g, m.c, m.rho, w, d_adj=y, want_wavelet_grad=True, ckpt=3)["grad_wavelet"]
+    lhs, rhs = np.sum(Fw * y), np.sum(w * Fty)
+    assert abs(lhs - rhs) <= 1e-10 * abs(lhs)
+    dc = rng.standard_normal(m.c.shape)
+    drho = rng.standard_normal(m.c.shape)
+    Jdm = O.born(g, m.c, m.rho, m.wavelet, dc, drho)
+    r = O.run(g, m.c, m.rho, m.wavelet, d_adj=y)
+    lhs = np.sum(Jdm * y)
+    rhs = np.sum(dc * r["grad_c"]) + np.sum(drho * r["grad_rho"])
+    assert abs(lhs - rhs) <= 1e-10 * abs(lhs)
+
+
+def test_p17_brute_force_gradient_fourth_order():
+    m = _order4(W.small_random_medium(1, 9, 8, 60, n_tx=2, n_rcv=4, npml=2, dup_receiver=True))
+    g = m.geom
+    rng = np.random.default_rng(101)
+    c_obs = (m.c * (1 + 0.02 * (rng.random(m.c.shape) - 0.5))).astype(np.float64)
+    obs = O.run(g, c_obs, m.rho, m.wavelet)["traces"]
+    r = O.run(g, m.c, m.rho, m.wavelet, d_obs=obs)
+    c0, r0 = m.c.astype(np.float64), m.rho.astype(np.float64)
+    J = lambda cc, rr: O.run(g, cc, rr, m.wavelet, d_obs=obs, gradient=False)["misfit"]
+    gc, gr = np.zeros_like(c0), np.zeros_like(c0)
+    eps = 1e-3
+    for iz in range(g.nz):
+        for ix in range(g.nx):
+            e = np.zeros_like(c0); e[iz, ix] = eps
+            gc[iz, ix] = (J(c0 + e, r0) - J(c0 - e, r0)) / (2 * eps)
+            gr[iz, ix] = (J(c0, r0 + e) - J(c0, r0 - e)) / (2 * eps)
+    assert rel_l2(r["grad_c"], gc) <= 1e-6
+    assert rel_l2(r["grad_rho"], gr) <= 1e-6
+
+
+def test_p17_density_scale_and_checkpoint_fourth_order():
+    m = _order4(W.small_random_medium(9, 20, 18, 100, n_tx=2, n_rcv=4, npml=3))
+    g = m.geom
+    a = O.run(g, m.c, m.rho, m.wavelet)["traces"]
+    b = O.run(g, m.c, m.rho.astype(np.float64) * 1.7, m.wavelet)["traces"]
+    assert rel_l2(b, a) <= 1e-13
+    obs = O.run(g, m.c.astype(np.float64) * 1.01, m.rho, m.wavelet)["traces"]
+    r = O.run(g, m.c, m.rho, m.wavelet, d_obs=obs)
+    s = np.sum(m.rho.astype(np.float64) * r["grad_rho"])
+    assert abs(s) <= 1e-12 * np.linalg.norm(m.rho) * np.linalg.norm(r["grad_rho"])
+    k = O.run(g, m.c, m.rho, m.wavelet, d_obs=obs, ckpt=7)
+    for key in ("traces", "grad_c", "grad_rho"):
+        assert np.array_equal(k[key], r[key]), key
+    # the second-order operator gives different traces
+    g2 = W.Geometry(**{**g.__dict__, "order": 2})
+    assert rel_l2(O.run(g2, m.c, m.rho, m.wavelet)["traces"], a) > 1e-3
+
+
+def test_p17_stability_bound_fourth_order():
+    """Without damping the fourth-order operator's largest eigenvalue gives
+    the limit c dt / h < 6/sqrt(98) = 0.606: 0.59 stays bounded, 0.63 grows."""
+    n = 41
+    amps = []
+    for cr in (0.59, 0.63):
+        h = 1e-3
+        dt = cr * h / 1500.0
+        g, ca, ra, w = _homog(n, 1500, h, dt, npml=0, src=[20 * n + 20], rcv=[[20 * n + 25]], f0=1.0 / (20 * dt))
+        g.order = 4
+        tr = O.run(g, ca, ra, w)["traces"][0, :, 0]
+        amps.append(np.max(np.abs(tr[-100:])))
+    assert np.isfinite(amps[0]) and amps[0] < 10.0
+    assert not np.isfinite(amps[1]) or amps[1] > 1e6

@@ -47,6 +47,7 @@ class Geometry:
     npml: int = NPML
     pml_r: float = 1e-3
     pml_cref: float = 1540.0
+    order: int = 2           # spatial order of the operator: 2 (eq. 2's 3x3 kernel) or 4
 
     @property
     def n_tx(self) -> int:
