@@ -42,7 +42,8 @@ extern "C" {
 typedef enum fwi_status {
     FWI_OK = 0,
     FWI_ERR_INVALID = 1,     /* bad argument: NULL pointer, size out of range, option unknown   */
-    FWI_ERR_CFL = 2,         /* unstable time step: (D_max dt)^2*4 + 8 (c_max dt/h)^2 >= 4, or   */
+    FWI_ERR_CFL = 2,         /* unstable time step: (D_max dt)^2*4 + k (c_max dt/h)^2 >= 4 with  */
+                             /* k = 8 (order 2) or 98/9 (order 4), or                           */
                              /* a cell's c above the declared c_max (found on the device)        */
     FWI_ERR_GEOMETRY = 3,    /* a source or receiver cell outside the grid                      */
     FWI_ERR_NOMEM = 4,       /* the library could not allocate its plan-owned device tables     */
@@ -114,6 +115,11 @@ typedef struct fwi_options {
                              /*    FWI_ERR_HIP                                                   */
     double mem_budget;       /* bytes the workspace may use; 0 = 60% of free device memory      */
     const char *tune_cache;  /* JSON cache path of the tile autotuner, or NULL                   */
+    int32_t order;           /* spatial order of the operator: 0 or 2 = the 5-point flux form of */
+                             /*    eq. 1-2; 4 = staggered fourth-order differences (one step per */
+                             /*    launch, rows 1, 2 or 4, not persistent; stability bound with  */
+                             /*    98/9 in place of 8)                                           */
+    int32_t reserved;
 } fwi_options;
 
 typedef struct fwi_plan fwi_plan;

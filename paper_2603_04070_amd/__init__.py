@@ -87,12 +87,14 @@ class Plan:
     (one transmit and one step per launch).  ``ckpt``: checkpoint interval K
     (0 = automatic, >= nt keeps every plane).  ``group``: transmits per work
     item (0 = automatic).  ``rows``: rows per thread of a 64 x 4*rows tile.
+    ``order``: 2 (the 5-point flux form) or 4 (staggered fourth-order
+    differences, one step per launch).
     """
 
     def __init__(self, grids: Sequence[GridSpec], dtype: str = "f32", mode: str = "batched",
                  ckpt: int = 0, group: int = 0, rows: int = 0, use_graph: bool = False,
                  acc_double: bool = False, mem_budget: float = 0.0, steps_per_launch: int = 0,
-                 forward_only: bool = False, persistent: bool = False, barrier_spin: int = 0):
+                 forward_only: bool = False, persistent: bool = False, barrier_spin: int = 0, order: int = 2):
         lib = _lib()
         self.grids = list(grids)
         self.dtype = dtype
@@ -118,6 +120,8 @@ class Plan:
         opt.persistent = int(bool(persistent))
         opt.barrier_spin = int(barrier_spin)
         opt.mem_budget = float(mem_budget)
+        opt.order = int(order)
+        self.order = int(order)
         self._h = C.c_void_p()
         dt = _abi.FWI_F64 if dtype == "f64" else _abi.FWI_F32
         st = lib.fwi_plan_create(C.byref(self._h), dt, arr, len(self.grids), C.byref(opt))
@@ -193,7 +197,7 @@ def _grid_array(grids, keep):
 
 
 def autotune(grids: Sequence[GridSpec], dtype: str = "f32", mode: str = "batched", group: int = 0,
-             cache: Optional[str] = None) -> dict:
+             cache: Optional[str] = None, order: int = 2) -> dict:
     """Time short device probes of the kernel variants for these grids and
     return the fastest ``steps_per_launch``, ``rows`` and (``group`` = 0)
     ``group`` (fwi_autotune)."""
@@ -203,6 +207,7 @@ def autotune(grids: Sequence[GridSpec], dtype: str = "f32", mode: str = "batched
     base = _abi.FwiOptions()
     base.mode = _abi.FWI_PLAIN if mode == "plain" else _abi.FWI_BATCHED
     base.group = int(group)
+    base.order = int(order)
     cache_b = cache.encode() if cache else None
     base.tune_cache = cache_b
     out = _abi.FwiOptions()

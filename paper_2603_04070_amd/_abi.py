@@ -48,6 +48,7 @@ class FwiOptions(C.Structure):
         ("persistent", C.c_int32), ("barrier_spin", C.c_int32),
         ("mem_budget", C.c_double),
         ("tune_cache", C.c_char_p),
+        ("order", C.c_int32), ("reserved", C.c_int32),
     ]
 
 

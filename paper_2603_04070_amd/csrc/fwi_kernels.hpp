@@ -1055,6 +1055,303 @@ __global__ __launch_bounds__(kBlock) void adj2_kernel(const Item<T, Acc>* __rest
     tile_adjoint2<T, G, Acc, R>(it, st, bt.y % it.tiles_x, bt.y / it.tiles_x, smem);
 }
 
+// ============================================================== fourth-order variant
+//
+// Staggered fourth-order differences: the flux through the face between
+// cells j and j+1 of a row or column is bt_f (9/8 (u_{j+1} - u_j) - 1/24
+// (u_{j+2} - u_{j-1})) with bt_f the mean of the two cells' bt, and the
+// operator is 9/8 (F_{+1/2} - F_{-1/2}) - 1/24 (F_{+3/2} - F_{-3/2}) summed
+// over both axes, so it reaches three cells out.  One step per launch: the
+// tile (64 x 4R cells) is staged in LDS grown by three cells.  Outside the
+// grid the fields are zero and bt repeats the nearest in-grid cell of the
+// row or column (the staged value at the clamped position), the border rule
+// of the second-order operator carried to the wider stencil.
+
+template <typename T, int G, int R, bool ADJ>
+struct Lds4 {
+    static constexpr int TZ = kWavesZ * R;
+    static constexpr int W = kTileX + 6, H = TZ + 6, N = W * H;       // tile grown by 3
+    static constexpr int P = (N + kBlock - 1) / kBlock;               // per-thread shares
+    // F[N] field (adjoint: lambda^t, then u^{t-1}), C[N][2] (q, bt)
+    static constexpr size_t bytes = (size_t)N * (G * (ADJ ? 2 : 1) + 2) * sizeof(T);
+};
+
+// D v at a face from the four values around it (v_{j-1}, v_j, v_{j+1}, v_{j+2}).
+template <typename T>
+__device__ __forceinline__ T d4(T vm, T v0, T v1, T v2)
+{
+#pragma clang fp contract(off)
+    return fma(T(9) / T(8), v1 - v0, (T(-1) / T(24)) * (v2 - vm));
+}
+
+// Combination of the four face fluxes around a cell.
+template <typename T>
+__device__ __forceinline__ T div4(T fm3, T fm1, T fp1, T fp3)
+{
+#pragma clang fp contract(off)
+    return fma(T(9) / T(8), fp1 - fm1, (T(-1) / T(24)) * (fp3 - fm3));
+}
+
+// Operator along one axis at LDS cell k (neighbour stride s) for every
+// transmit: L += 9/8 (F(k) - F(k-s)) - 1/24 (F(k+s) - F(k-2s)), F(m) the flux
+// through the face between cells m and m+s of the field V (times Q when QV).
+template <typename T, int G, bool QV>
+__device__ __forceinline__ void lap4_axis(const Vec<T, G>* V, const T* C, int k, int s, Vec<T, G>& L)
+{
+    Vec<T, G> v[7];
+    T q[7], bt[5];
+#pragma unroll
+    for (int i = 0; i < 7; ++i) {
+        v[i] = V[k + (i - 3) * s];
+        q[i] = QV ? C[2 * (k + (i - 3) * s)] : T(1);
+    }
+#pragma unroll
+    for (int i = 0; i < 5; ++i) bt[i] = C[2 * (k + (i - 2) * s) + 1];
+    const T hf = T(0.5);
+    const T b32 = hf * (bt[0] + bt[1]), b12 = hf * (bt[1] + bt[2]), p12 = hf * (bt[2] + bt[3]),
+            p32 = hf * (bt[3] + bt[4]);
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        T w[7];
+#pragma unroll
+        for (int i = 0; i < 7; ++i) w[i] = QV ? q[i] * v[i].v[g] : v[i].v[g];
+        const T fm3 = b32 * d4<T>(w[0], w[1], w[2], w[3]);
+        const T fm1 = b12 * d4<T>(w[1], w[2], w[3], w[4]);
+        const T fp1 = p12 * d4<T>(w[2], w[3], w[4], w[5]);
+        const T fp3 = p32 * d4<T>(w[3], w[4], w[5], w[6]);
+        L.v[g] += div4<T>(fm3, fm1, fp1, fp3);
+    }
+}
+
+// Imaging of one axis at LDS cell k, position i of n along the axis:
+// S_b += sum over the faces whose bt involve the cell of its share of
+// (D u)_f (D w)_f, w = q lambda: half of each neighbouring face, the whole
+// face where the neighbour is a ghost repeating this cell, and the face
+// between the two ghosts beyond a border cell.
+template <typename T, int G, typename Acc>
+__device__ __forceinline__ void image4_axis(const Vec<T, G>* U, const Vec<T, G>* Lm, const T* C, int k, int s,
+                                            int i, int n, Acc& sb)
+{
+    Vec<T, G> u[7], l[7];
+    T q[7];
+#pragma unroll
+    for (int j = 0; j < 7; ++j) {
+        u[j] = U[k + (j - 3) * s];
+        l[j] = Lm[k + (j - 3) * s];
+        q[j] = C[2 * (k + (j - 3) * s)];
+    }
+    const T hf = T(0.5);
+    const T wm = i == 0 ? T(1) : hf, wp = i == n - 1 ? T(1) : hf;
+    const T gm = i == 0 ? T(1) : T(0), gp = i == n - 1 ? T(1) : T(0);
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        T w[7];
+#pragma unroll
+        for (int j = 0; j < 7; ++j) w[j] = q[j] * l[j].v[g];
+        // faces between cells (k-2s, k-s), (k-s, k), (k, k+s), (k+s, k+2s)
+        const T Gm3 = d4<T>(u[0].v[g], u[1].v[g], u[2].v[g], u[3].v[g]) * d4<T>(w[0], w[1], w[2], w[3]);
+        const T Gm1 = d4<T>(u[1].v[g], u[2].v[g], u[3].v[g], u[4].v[g]) * d4<T>(w[1], w[2], w[3], w[4]);
+        const T Gp1 = d4<T>(u[2].v[g], u[3].v[g], u[4].v[g], u[5].v[g]) * d4<T>(w[2], w[3], w[4], w[5]);
+        const T Gp3 = d4<T>(u[3].v[g], u[4].v[g], u[5].v[g], u[6].v[g]) * d4<T>(w[3], w[4], w[5], w[6]);
+        sb += Acc(wm * Gm1 + wp * Gp1 + gm * Gm3 + gp * Gp3);
+    }
+}
+
+// Stage a field (zero outside the grid) and (q, bt) at clamped positions on
+// the tile grown by three.
+template <typename T, int G, typename Acc, int P, int W, int N>
+__device__ __forceinline__ void stage4(const Item<T, Acc>& it, const T* f, int x0, int z0, int tid,
+                                       Vec<T, G>* F, T* C)
+{
+    const int nx = it.nx, nz = it.nz;
+    Vec<T, G> fv[P];
+    T qv[P], bv[P];
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+        const int c = tid + i * kBlock;
+        const int gx = x0 - 3 + c % W, gz = z0 - 3 + c / W;
+        const bool in = c < N && gx >= 0 && gx < nx && gz >= 0 && gz < nz;
+        const int cx = min(max(gx, 0), nx - 1), cz = min(max(gz, 0), nz - 1);
+        const int64_t xc = c < N ? (int64_t)cz * nx + cx : 0;
+        fv[i] = vkeep<T, G>(in, vload<T, G>(f, in ? (int64_t)gz * nx + gx : 0));
+        qv[i] = ldg(it.coef, 2 * xc);
+        bv[i] = ldg(it.coef, 2 * xc + 1);
+    }
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+        const int c = tid + i * kBlock;
+        if (c < N) {
+            F[c] = fv[i];
+            C[2 * c] = qv[i];
+            C[2 * c + 1] = bv[i];
+        }
+    }
+}
+
+template <typename T, int G, typename Acc, int R>
+__device__ void tile_forward4(const Item<T, Acc>& it, const Step& st, int tile_x, int tile_z, bool sample,
+                              unsigned char* smem)
+{
+    using L = Lds4<T, G, R, false>;
+    const int nx = it.nx, nz = it.nz, n = st.n;
+    Vec<T, G>* U = reinterpret_cast<Vec<T, G>*>(smem);
+    T* C = reinterpret_cast<T*>(U + L::N);
+    const T* cur = fwd_plane(it, st, n);
+    const T* vin = vel_in(it, st, n);
+    T* out = it.seg + (int64_t)(n % it.K) * it.plane;
+    T* vout = vel_out(it, n + 1);
+    T* ckv = ckpt_pair(it, st, n + 1);
+    const Src<T, G> src = sources<T, G>(it, n);
+    const Span rcv = sample ? span_of(it.tile_off, tile_z * it.tiles_x + tile_x) : Span{0, 0};
+    const int x0 = tile_x * kTileX, z0 = tile_z * L::TZ;
+    const int tid = threadIdx.y * kTileX + threadIdx.x;
+    const int ix = x0 + (int)threadIdx.x;
+    Vec<T, G> vt[R];
+    T ezd[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        const int iz = z0 + (int)threadIdx.y * R + k;
+        const bool in = ix < nx && iz < nz;
+        vt[k] = vload<T, G>(vin, in ? (int64_t)iz * nx + ix : 0);
+        ezd[k] = ldg(it.ez, iz < nz ? iz : 0);
+    }
+    const T exd = ldg(it.ex, ix < nx ? ix : 0);
+    stage4<T, G, Acc, L::P, L::W, L::N>(it, cur, x0, z0, tid, U, C);
+    __syncthreads();
+    if (ix < nx) {
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            const int ez = (int)threadIdx.y * R + k, iz = z0 + ez;
+            if (iz < nz) {
+                const int kk = (ez + 3) * L::W + threadIdx.x + 3;
+                const int64_t x = (int64_t)iz * nx + ix;
+                Vec<T, G> Lu = vzero<T, G>();
+                lap4_axis<T, G, false>(U, C, kk, 1, Lu);
+                lap4_axis<T, G, false>(U, C, kk, L::W, Lu);
+                T nb, c2;
+                damp_inc<T>(exd + ezd[k], nb, c2);
+                const T q = C[2 * kk];
+                const Vec<T, G> u0 = U[kk];
+                Vec<T, G> r, rv;
+#pragma unroll
+                for (int g = 0; g < G; ++g) {
+#pragma clang fp contract(off)
+                    T v = fma(q, Lu.v[g], fma(nb, vt[k].v[g], c2 * u0.v[g]));
+                    if ((int)x == src.cell[g]) v += src.w[g];
+                    rv.v[g] = v;
+                    r.v[g] = u0.v[g] + v;
+                }
+                vstore<T, G>(out, x, r);
+                vstore<T, G>(vout, x, rv);
+                if (ckv) {
+                    vstore<T, G>(ckv, x, rv);
+                    vstore<T, G>(ckv + it.plane, x, r);
+                }
+            }
+        }
+    }
+    sample_tile(it, rcv, n, out, (const T*)nullptr);
+}
+
+template <typename T, int G, typename Acc, int R>
+__device__ void tile_adjoint4(const Item<T, Acc>& it, const Step& st, int tile_x, int tile_z, unsigned char* smem)
+{
+    using L = Lds4<T, G, R, true>;
+    const int nx = it.nx, nz = it.nz, t = st.n;
+    const int64_t P = it.plane, ncell = (int64_t)nx * nz;
+    Vec<T, G>* Lm = reinterpret_cast<Vec<T, G>*>(smem);                 // lam^t
+    Vec<T, G>* U = Lm + L::N;                                           // u^{t-1}
+    T* C = reinterpret_cast<T*>(U + L::N);
+    const T* cur = it.lam + (int64_t)(t % it.nlam) * P;                 // lam^t
+    const T* p1 = it.lam + (int64_t)((t + 1) % it.nlam) * P;            // lam^{t+1}
+    T* out = it.lam + (int64_t)((t - 1) % it.nlam) * P;                 // lam^{t-1}
+    const T* um = it.seg + (int64_t)((t - 2) % it.K) * P;               // u^{t-1}
+    Acc* accK = it.acc;
+    Acc* accB = it.acc + ncell;
+    const int tile = tile_z * it.tiles_x + tile_x;
+    const Span rcv = span_of(it.tile_off, tile);
+    const int x0 = tile_x * kTileX, z0 = tile_z * L::TZ;
+    const int tid = threadIdx.y * kTileX + threadIdx.x;
+    const int ix = x0 + (int)threadIdx.x;
+    Vec<T, G> lp[R];
+    Acc sK[R], sB[R];
+    T ezd[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        const int iz = z0 + (int)threadIdx.y * R + k;
+        const bool in = ix < nx && iz < nz;
+        const int64_t x = in ? (int64_t)iz * nx + ix : 0;
+        lp[k] = vload<T, G>(p1, x);
+        sK[k] = ldg(accK, x);
+        sB[k] = ldg(accB, x);
+        ezd[k] = ldg(it.ez, iz < nz ? iz : 0);
+    }
+    const T exd = ldg(it.ex, ix < nx ? ix : 0);
+    // the field loader stages (q, bt) twice; the second copy is the same
+    stage4<T, G, Acc, L::P, L::W, L::N>(it, cur, x0, z0, tid, Lm, C);
+    stage4<T, G, Acc, L::P, L::W, L::N>(it, um, x0, z0, tid, U, C);
+    __syncthreads();
+    if (ix < nx) {
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            const int ez = (int)threadIdx.y * R + k, iz = z0 + ez;
+            if (iz < nz) {
+                const int kk = (ez + 3) * L::W + threadIdx.x + 3;
+                const int64_t x = (int64_t)iz * nx + ix;
+                Vec<T, G> Lw = vzero<T, G>(), Lu = vzero<T, G>();
+                lap4_axis<T, G, true>(Lm, C, kk, 1, Lw);
+                lap4_axis<T, G, true>(Lm, C, kk, L::W, Lw);
+                lap4_axis<T, G, false>(U, C, kk, 1, Lu);
+                lap4_axis<T, G, false>(U, C, kk, L::W, Lu);
+                T a, b;
+                damp_coeffs<T>(exd + ezd[k], a, b);
+                const Vec<T, G> l0 = Lm[kk];
+                Vec<T, G> r;
+                Acc sk = Acc(0), sb = Acc(0);
+#pragma unroll
+                for (int g = 0; g < G; ++g) {
+#pragma clang fp contract(off)
+                    r.v[g] = fma(a, l0.v[g], fma(b, lp[k].v[g], Lw.v[g]));
+                    sk += Acc(l0.v[g] * Lu.v[g]);
+                }
+                image4_axis<T, G, Acc>(U, Lm, C, kk, 1, ix, nx, sb);
+                image4_axis<T, G, Acc>(U, Lm, C, kk, L::W, iz, nz, sb);
+                vstore<T, G>(out, x, r);
+                stg(accK, x, sK[k] + sk);
+                stg(accB, x, sB[k] + sb);
+            }
+        }
+    }
+    // adjoint source of lam^{t-1}: sample t-2
+    inject_tile(it, rcv, t - 2, out);
+}
+
+template <typename T, int G, typename Acc, int R>
+__global__ __launch_bounds__(kBlock) void fwd4_kernel(const Item<T, Acc>* __restrict__ items,
+                                                       const int2* __restrict__ blocks, int s, int mode)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int2 bt = blocks[blockIdx.x];
+    if (bt.x < 0) return;
+    const Item<T, Acc>& it = items[bt.x];
+    const Step st = item_step(it, s, mode);
+    if (st.phase != kFwd && st.phase != kRecomp) return;
+    tile_forward4<T, G, Acc, R>(it, st, bt.y % it.tiles_x, bt.y / it.tiles_x, st.phase == kFwd && it.sample, smem);
+}
+
+template <typename T, int G, typename Acc, int R>
+__global__ __launch_bounds__(kBlock) void adj4_kernel(const Item<T, Acc>* __restrict__ items,
+                                                       const int2* __restrict__ blocks, int s, int mode)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int2 bt = blocks[blockIdx.x];
+    if (bt.x < 0) return;
+    const Item<T, Acc>& it = items[bt.x];
+    const Step st = item_step(it, s, mode);
+    if (st.phase != kAdj) return;
+    tile_adjoint4<T, G, Acc, R>(it, st, bt.y % it.tiles_x, bt.y / it.tiles_x, smem);
+}
+
 // ---------------------------------------------------------------- persistent form
 //
 // One launch runs every step of a wave: each workgroup walks its share of

@@ -65,7 +65,7 @@ struct MediumPlan {
 struct fwi_plan {
     fwi_dtype dtype = FWI_F32;
     fwi_options opt{};
-    int G = 1, rows = 4, S = 1, nlam = 2;
+    int G = 1, rows = 4, S = 1, nlam = 2, order = 2;
     bool acc_double = false;
     size_t tsize = 4, asize = 4;
     std::vector<MediumPlan> media;
@@ -140,7 +140,7 @@ double prof(int i, int n, int N, double dmax)
 }
 
 // Host-side validation of one grid (no HIP call).
-fwi_status validate_grid(const fwi_grid& g, int idx, std::string& msg)
+fwi_status validate_grid(const fwi_grid& g, int idx, std::string& msg, int order)
 {
     char buf[256];
     auto bad = [&](fwi_status st, const char* what) {
@@ -169,9 +169,14 @@ fwi_status validate_grid(const fwi_grid& g, int idx, std::string& msg)
         }
     }
     // frozen-coefficient stability of the damped leapfrog update:
-    // (D dt)^2 + c^2 dt^2 * 8/h^2 < 4 with D = 2 D_max in the corners
+    // (D dt)^2 + c^2 dt^2 k/h^2 < 4 with D = 2 D_max in the corners and k the
+    // operator's largest eigenvalue times h^2/b: 2 x 4 for the 5-point form,
+    // 2 x (9/8 * 2 + 1/24 * 2)^2 = 98/9 for the fourth-order form
     const double e = 2.0 * dmax_of(g) * g.dt, cr = g.c_max * g.dt / g.h;
-    if (e * e + 8.0 * cr * cr >= 4.0) return bad(FWI_ERR_CFL, "unstable: 4 (Dmax dt)^2 + 8 (c_max dt/h)^2 >= 4");
+    const double k = order == 4 ? 98.0 / 9.0 : 8.0;
+    if (e * e + k * cr * cr >= 4.0)
+        return bad(FWI_ERR_CFL, order == 4 ? "unstable: 4 (Dmax dt)^2 + 98/9 (c_max dt/h)^2 >= 4"
+                                           : "unstable: 4 (Dmax dt)^2 + 8 (c_max dt/h)^2 >= 4");
     return FWI_OK;
 }
 
@@ -190,12 +195,31 @@ void launch2(int kind, dim3 grid, hipStream_t st, const Item<T, Acc>* it, const 
         hipLaunchKernelGGL((adj2_kernel<T, G, Acc, R>), grid, blk, lds_a, st, it, blocks, s, mode);
 }
 
+// Fourth-order one-step launches (kind 0 forward, 2 adjoint), R = 1, 2, 4.
+template <typename T, typename Acc, int G, int R>
+void launch4(int kind, dim3 grid, hipStream_t st, const Item<T, Acc>* it, const int2* blocks, int s, int mode)
+{
+    const dim3 blk(kTileX, kWavesZ);
+    constexpr size_t lds_f = Lds4<T, G, R, false>::bytes;
+    constexpr size_t lds_a = Lds4<T, G, R, true>::bytes;
+    if (kind == 0)
+        hipLaunchKernelGGL((fwd4_kernel<T, G, Acc, R>), grid, blk, lds_f, st, it, blocks, s, mode);
+    else
+        hipLaunchKernelGGL((adj4_kernel<T, G, Acc, R>), grid, blk, lds_a, st, it, blocks, s, mode);
+}
+
 template <typename T, typename Acc, int G>
 void launch_step(int kind, dim3 grid, hipStream_t st, const void* items, const int2* blocks, int s, int mode,
-                 int rows)
+                 int rows, int order)
 {
     const auto* it = reinterpret_cast<const Item<T, Acc>*>(items);
     const dim3 blk(kTileX, kWavesZ);
+    if (order == 4) {
+        if (rows == 1) launch4<T, Acc, G, 1>(kind, grid, st, it, blocks, s, mode);
+        else if (rows == 2) launch4<T, Acc, G, 2>(kind, grid, st, it, blocks, s, mode);
+        else launch4<T, Acc, G, 4>(kind, grid, st, it, blocks, s, mode);
+        return;
+    }
     if (kind == 0) {
         hipLaunchKernelGGL((fwd1_kernel<T, G, Acc>), grid, blk, 0, st, it, blocks, s, mode, rows);
     } else if (kind == 2) {
@@ -220,9 +244,24 @@ hipError_t allow_lds()
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)Lds2<T, G, R, true>::bytes);
 }
 
-template <typename T, typename Acc, int G>
-hipError_t allow_lds_r(int rows)
+template <typename T, typename Acc, int G, int R>
+hipError_t allow_lds4()
 {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&fwd4_kernel<T, G, Acc, R>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)Lds4<T, G, R, false>::bytes);
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(&adj4_kernel<T, G, Acc, R>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)Lds4<T, G, R, true>::bytes);
+}
+
+template <typename T, typename Acc, int G>
+hipError_t allow_lds_r(int rows, int order)
+{
+    if (order == 4) {
+        if (rows == 1) return allow_lds4<T, Acc, G, 1>();
+        if (rows == 2) return allow_lds4<T, Acc, G, 2>();
+        return allow_lds4<T, Acc, G, 4>();
+    }
     if (rows == 1) return allow_lds<T, Acc, G, 1>();
     if (rows == 2) return allow_lds<T, Acc, G, 2>();
     return allow_lds<T, Acc, G, 4>();
@@ -230,32 +269,32 @@ hipError_t allow_lds_r(int rows)
 
 template <typename T, typename Acc>
 void launch_step_g(int G, int kind, dim3 grid, hipStream_t st, const void* items, const int2* blocks, int s,
-                   int mode, int rows)
+                   int mode, int rows, int order)
 {
-    if (G == 1) launch_step<T, Acc, 1>(kind, grid, st, items, blocks, s, mode, rows);
-    else if (G == 2) launch_step<T, Acc, 2>(kind, grid, st, items, blocks, s, mode, rows);
-    else launch_step<T, Acc, 4>(kind, grid, st, items, blocks, s, mode, rows);
+    if (G == 1) launch_step<T, Acc, 1>(kind, grid, st, items, blocks, s, mode, rows, order);
+    else if (G == 2) launch_step<T, Acc, 2>(kind, grid, st, items, blocks, s, mode, rows, order);
+    else launch_step<T, Acc, 4>(kind, grid, st, items, blocks, s, mode, rows, order);
 }
 
 void step(fwi_plan* p, int kind, dim3 grid, hipStream_t st, const int2* blocks, int s, int mode)
 {
     if (p->dtype == FWI_F64)
-        launch_step_g<double, double>(p->G, kind, grid, st, p->d_items, blocks, s, mode, p->rows);
+        launch_step_g<double, double>(p->G, kind, grid, st, p->d_items, blocks, s, mode, p->rows, p->order);
     else if (p->acc_double)
-        launch_step_g<float, double>(p->G, kind, grid, st, p->d_items, blocks, s, mode, p->rows);
+        launch_step_g<float, double>(p->G, kind, grid, st, p->d_items, blocks, s, mode, p->rows, p->order);
     else
-        launch_step_g<float, float>(p->G, kind, grid, st, p->d_items, blocks, s, mode, p->rows);
+        launch_step_g<float, float>(p->G, kind, grid, st, p->d_items, blocks, s, mode, p->rows, p->order);
 }
 
 hipError_t allow_lds_plan(const fwi_plan* p)
 {
-    if (p->S != 2) return hipSuccess;
+    if (p->S != 2 && p->order != 4) return hipSuccess;
     auto pick = [&](auto t, auto a) -> hipError_t {
         using T = decltype(t);
         using A = decltype(a);
-        if (p->G == 1) return allow_lds_r<T, A, 1>(p->rows);
-        if (p->G == 2) return allow_lds_r<T, A, 2>(p->rows);
-        return allow_lds_r<T, A, 4>(p->rows);
+        if (p->G == 1) return allow_lds_r<T, A, 1>(p->rows, p->order);
+        if (p->G == 2) return allow_lds_r<T, A, 2>(p->rows, p->order);
+        return allow_lds_r<T, A, 4>(p->rows, p->order);
     };
     if (p->dtype == FWI_F64) return pick(double(), double());
     if (p->acc_double) return pick(float(), double());
@@ -433,9 +472,16 @@ static fwi_status create_impl(fwi_plan* p, fwi_dtype dtype, const fwi_grid* grid
     if (o.persistent != 0 && o.persistent != 1) return fail(p, FWI_ERR_INVALID, "persistent must be 0 or 1");
     if (o.persistent && o.mode != FWI_BATCHED) return fail(p, FWI_ERR_INVALID, "persistent requires FWI_BATCHED");
     if (o.barrier_spin < 0) return fail(p, FWI_ERR_INVALID, "barrier_spin must be >= 0");
+    if (o.order != 0 && o.order != 2 && o.order != 4) return fail(p, FWI_ERR_INVALID, "order must be 0, 2 or 4");
+    if (o.order == 4) {
+        if (o.persistent) return fail(p, FWI_ERR_INVALID, "the fourth-order operator has no persistent form");
+        if (o.steps_per_launch == 2) return fail(p, FWI_ERR_INVALID, "the fourth-order operator runs one step per launch");
+        if (o.rows != 0 && o.rows != 1 && o.rows != 2 && o.rows != 4)
+            return fail(p, FWI_ERR_INVALID, "the fourth-order operator needs rows of 1, 2 or 4");
+    }
     for (int i = 0; i < n_media; ++i) {
         std::string msg;
-        fwi_status st = validate_grid(grids[i], i, msg);
+        fwi_status st = validate_grid(grids[i], i, msg, o.order);
         if (st != FWI_OK) return fail(p, st, msg);
     }
 
@@ -451,7 +497,15 @@ static fwi_status create_impl(fwi_plan* p, fwi_dtype dtype, const fwi_grid* grid
         const size_t ts = dtype == FWI_F64 ? 8 : 4;
         return (n0 * (p->G + 2) + 3 * n1 * p->G) * ts <= kLdsBytes;
     };
-    if (o.steps_per_launch == 2) {
+    p->order = o.order == 4 ? 4 : 2;
+    if (p->order == 4) {
+        p->S = 1;
+        p->rows = o.rows ? o.rows : 2;
+        const size_t ts = dtype == FWI_F64 ? 8 : 4;
+        const size_t n4 = (size_t)(kTileX + 6) * (kWavesZ * p->rows + 6);
+        if (n4 * (2 * p->G + 2) * ts > kLdsBytes)
+            return fail(p, FWI_ERR_INVALID, "the fourth-order tile of these rows does not fit the LDS");
+    } else if (o.steps_per_launch == 2) {
         p->S = 2;
         p->rows = o.rows ? o.rows : 2;
         if (!two_step_ok(p->rows))
@@ -1151,9 +1205,9 @@ std::string tune_key(const char* arch, fwi_dtype dtype, const fwi_options& o, in
     char gs[16];
     if (G) std::snprintf(gs, sizeof gs, "G%d", G);
     else std::snprintf(gs, sizeof gs, "Gauto");
-    std::snprintf(buf, sizeof buf, "%s|%s|%s|%s|c%ld|i%ld", a.c_str(), dtype == FWI_F64 ? "f64" : "f32",
-                  o.mode == FWI_PLAIN ? "plain" : "batched", gs, std::lround(std::log2(cells / n)),
-                  std::lround(std::log2((double)items)));
+    std::snprintf(buf, sizeof buf, "%s|%s|%s|o%d|%s|c%ld|i%ld", a.c_str(), dtype == FWI_F64 ? "f64" : "f32",
+                  o.mode == FWI_PLAIN ? "plain" : "batched", o.order == 4 ? 4 : 2, gs,
+                  std::lround(std::log2(cells / n)), std::lround(std::log2((double)items)));
     return buf;
 }
 
@@ -1233,7 +1287,7 @@ extern "C" fwi_status fwi_autotune(fwi_dtype dtype, const fwi_grid* grids, int32
     if (base) o = *base;
     for (int i = 0; i < n_media; ++i) {
         std::string msg;
-        fwi_status st = validate_grid(grids[i], i, msg);
+        fwi_status st = validate_grid(grids[i], i, msg, o.order);
         if (st != FWI_OK) { g_create_error = msg; return st; }
     }
     // transmits per work item: the caller's, else searched over 4, 2, 1 (plain: 1)

@@ -103,6 +103,11 @@ def _grid(**kw):
     ({}, dict(mode="plain", use_graph=True), 1),
     ({}, dict(steps_per_launch=2, rows=3), 1),
     ({}, dict(steps_per_launch=3), 1),
+    ({}, dict(order=3), 1),
+    (dict(c_max=3100.0), dict(order=4), 2),                 # c dt/h = 0.62 > 0.606 (order 4 only)
+    ({}, dict(order=4, persistent=True), 1),
+    ({}, dict(order=4, steps_per_launch=2), 1),
+    ({}, dict(order=4, rows=8), 1),
 ])
 def test_host_validation(kw, opt, code):
     with pytest.raises(F.FwiError) as e:
