@@ -1094,17 +1094,14 @@ __device__ __forceinline__ T div4(T fm3, T fm1, T fp1, T fp3)
 
 // Operator along one axis at LDS cell k (neighbour stride s) for every
 // transmit: L += 9/8 (F(k) - F(k-s)) - 1/24 (F(k+s) - F(k-2s)), F(m) the flux
-// through the face between cells m and m+s of the field V (times Q when QV).
-template <typename T, int G, bool QV>
+// through the face between cells m and m+s of the field V.
+template <typename T, int G>
 __device__ __forceinline__ void lap4_axis(const Vec<T, G>* V, const T* C, int k, int s, Vec<T, G>& L)
 {
     Vec<T, G> v[7];
-    T q[7], bt[5];
+    T bt[5];
 #pragma unroll
-    for (int i = 0; i < 7; ++i) {
-        v[i] = V[k + (i - 3) * s];
-        q[i] = QV ? C[2 * (k + (i - 3) * s)] : T(1);
-    }
+    for (int i = 0; i < 7; ++i) v[i] = V[k + (i - 3) * s];
 #pragma unroll
     for (int i = 0; i < 5; ++i) bt[i] = C[2 * (k + (i - 2) * s) + 1];
     const T hf = T(0.5);
@@ -1112,48 +1109,89 @@ __device__ __forceinline__ void lap4_axis(const Vec<T, G>* V, const T* C, int k,
             p32 = hf * (bt[3] + bt[4]);
 #pragma unroll
     for (int g = 0; g < G; ++g) {
-        T w[7];
-#pragma unroll
-        for (int i = 0; i < 7; ++i) w[i] = QV ? q[i] * v[i].v[g] : v[i].v[g];
-        const T fm3 = b32 * d4<T>(w[0], w[1], w[2], w[3]);
-        const T fm1 = b12 * d4<T>(w[1], w[2], w[3], w[4]);
-        const T fp1 = p12 * d4<T>(w[2], w[3], w[4], w[5]);
-        const T fp3 = p32 * d4<T>(w[3], w[4], w[5], w[6]);
+        const T fm3 = b32 * d4<T>(v[0].v[g], v[1].v[g], v[2].v[g], v[3].v[g]);
+        const T fm1 = b12 * d4<T>(v[1].v[g], v[2].v[g], v[3].v[g], v[4].v[g]);
+        const T fp1 = p12 * d4<T>(v[2].v[g], v[3].v[g], v[4].v[g], v[5].v[g]);
+        const T fp3 = p32 * d4<T>(v[3].v[g], v[4].v[g], v[5].v[g], v[6].v[g]);
         L.v[g] += div4<T>(fm3, fm1, fp1, fp3);
     }
 }
 
-// Imaging of one axis at LDS cell k, position i of n along the axis:
-// S_b += sum over the faces whose bt involve the cell of its share of
-// (D u)_f (D w)_f, w = q lambda: half of each neighbouring face, the whole
-// face where the neighbour is a ghost repeating this cell, and the face
-// between the two ghosts beyond a border cell.
+// Adjoint work of one axis at LDS cell k (position i of n along the axis),
+// from one read of the seven lambda^t, u^{t-1} and q values and five bt
+// around it: Lw += operator of w = q lambda, Lu += operator of u, and the
+// imaging share sb += sum over the faces whose bt involve the cell of its
+// part of (D u)_f (D w)_f: half of each neighbouring face, the whole face
+// where the neighbour is a ghost repeating this cell, and the face between
+// the two ghosts beyond a border cell.
 template <typename T, int G, typename Acc>
-__device__ __forceinline__ void image4_axis(const Vec<T, G>* U, const Vec<T, G>* Lm, const T* C, int k, int s,
-                                            int i, int n, Acc& sb)
+__device__ __forceinline__ void adj4_axis(const Vec<T, G>* Lm, const Vec<T, G>* U, const T* C, int k, int s, int i,
+                                          int n, Vec<T, G>& Lw, Vec<T, G>& Lu, Acc& sb)
 {
-    Vec<T, G> u[7], l[7];
-    T q[7];
+    Vec<T, G> l[7], u[7];
+    T q[7], bt[5];
 #pragma unroll
     for (int j = 0; j < 7; ++j) {
-        u[j] = U[k + (j - 3) * s];
         l[j] = Lm[k + (j - 3) * s];
+        u[j] = U[k + (j - 3) * s];
         q[j] = C[2 * (k + (j - 3) * s)];
     }
+#pragma unroll
+    for (int j = 0; j < 5; ++j) bt[j] = C[2 * (k + (j - 2) * s) + 1];
     const T hf = T(0.5);
+    const T b32 = hf * (bt[0] + bt[1]), b12 = hf * (bt[1] + bt[2]), p12 = hf * (bt[2] + bt[3]),
+            p32 = hf * (bt[3] + bt[4]);
     const T wm = i == 0 ? T(1) : hf, wp = i == n - 1 ? T(1) : hf;
     const T gm = i == 0 ? T(1) : T(0), gp = i == n - 1 ? T(1) : T(0);
 #pragma unroll
     for (int g = 0; g < G; ++g) {
-        T w[7];
+        T w[7], v[7];
 #pragma unroll
-        for (int j = 0; j < 7; ++j) w[j] = q[j] * l[j].v[g];
-        // faces between cells (k-2s, k-s), (k-s, k), (k, k+s), (k+s, k+2s)
-        const T Gm3 = d4<T>(u[0].v[g], u[1].v[g], u[2].v[g], u[3].v[g]) * d4<T>(w[0], w[1], w[2], w[3]);
-        const T Gm1 = d4<T>(u[1].v[g], u[2].v[g], u[3].v[g], u[4].v[g]) * d4<T>(w[1], w[2], w[3], w[4]);
-        const T Gp1 = d4<T>(u[2].v[g], u[3].v[g], u[4].v[g], u[5].v[g]) * d4<T>(w[2], w[3], w[4], w[5]);
-        const T Gp3 = d4<T>(u[3].v[g], u[4].v[g], u[5].v[g], u[6].v[g]) * d4<T>(w[3], w[4], w[5], w[6]);
-        sb += Acc(wm * Gm1 + wp * Gp1 + gm * Gm3 + gp * Gp3);
+        for (int j = 0; j < 7; ++j) {
+            w[j] = q[j] * l[j].v[g];
+            v[j] = u[j].v[g];
+        }
+        const T dw3 = d4<T>(w[0], w[1], w[2], w[3]), dw1 = d4<T>(w[1], w[2], w[3], w[4]);
+        const T ew1 = d4<T>(w[2], w[3], w[4], w[5]), ew3 = d4<T>(w[3], w[4], w[5], w[6]);
+        const T du3 = d4<T>(v[0], v[1], v[2], v[3]), du1 = d4<T>(v[1], v[2], v[3], v[4]);
+        const T eu1 = d4<T>(v[2], v[3], v[4], v[5]), eu3 = d4<T>(v[3], v[4], v[5], v[6]);
+        Lw.v[g] += div4<T>(b32 * dw3, b12 * dw1, p12 * ew1, p32 * ew3);
+        Lu.v[g] += div4<T>(b32 * du3, b12 * du1, p12 * eu1, p32 * eu3);
+        sb += Acc(wm * (du1 * dw1) + wp * (eu1 * ew1) + gm * (du3 * dw3) + gp * (eu3 * ew3));
+    }
+}
+
+// Stage two fields (zero outside the grid) and (q, bt) at clamped positions
+// on the tile grown by three, all loads issued before the first LDS store.
+template <typename T, int G, typename Acc, int P, int W, int N>
+__device__ __forceinline__ void stage4x2(const Item<T, Acc>& it, const T* f1, const T* f2, int x0, int z0, int tid,
+                                         Vec<T, G>* F1, Vec<T, G>* F2, T* C)
+{
+    const int nx = it.nx, nz = it.nz;
+    Vec<T, G> a[P], b[P];
+    T qv[P], bv[P];
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+        const int c = tid + i * kBlock;
+        const int gx = x0 - 3 + c % W, gz = z0 - 3 + c / W;
+        const bool in = c < N && gx >= 0 && gx < nx && gz >= 0 && gz < nz;
+        const int cx = min(max(gx, 0), nx - 1), cz = min(max(gz, 0), nz - 1);
+        const int64_t xc = c < N ? (int64_t)cz * nx + cx : 0;
+        const int64_t xi = in ? (int64_t)gz * nx + gx : 0;
+        a[i] = vkeep<T, G>(in, vload<T, G>(f1, xi));
+        b[i] = vkeep<T, G>(in, vload<T, G>(f2, xi));
+        qv[i] = ldg(it.coef, 2 * xc);
+        bv[i] = ldg(it.coef, 2 * xc + 1);
+    }
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+        const int c = tid + i * kBlock;
+        if (c < N) {
+            F1[c] = a[i];
+            F2[c] = b[i];
+            C[2 * c] = qv[i];
+            C[2 * c + 1] = bv[i];
+        }
     }
 }
 
@@ -1226,8 +1264,8 @@ __device__ void tile_forward4(const Item<T, Acc>& it, const Step& st, int tile_x
                 const int kk = (ez + 3) * L::W + threadIdx.x + 3;
                 const int64_t x = (int64_t)iz * nx + ix;
                 Vec<T, G> Lu = vzero<T, G>();
-                lap4_axis<T, G, false>(U, C, kk, 1, Lu);
-                lap4_axis<T, G, false>(U, C, kk, L::W, Lu);
+                lap4_axis<T, G>(U, C, kk, 1, Lu);
+                lap4_axis<T, G>(U, C, kk, L::W, Lu);
                 T nb, c2;
                 damp_inc<T>(exd + ezd[k], nb, c2);
                 const T q = C[2 * kk];
@@ -1287,9 +1325,7 @@ __device__ void tile_adjoint4(const Item<T, Acc>& it, const Step& st, int tile_x
         ezd[k] = ldg(it.ez, iz < nz ? iz : 0);
     }
     const T exd = ldg(it.ex, ix < nx ? ix : 0);
-    // the field loader stages (q, bt) twice; the second copy is the same
-    stage4<T, G, Acc, L::P, L::W, L::N>(it, cur, x0, z0, tid, Lm, C);
-    stage4<T, G, Acc, L::P, L::W, L::N>(it, um, x0, z0, tid, U, C);
+    stage4x2<T, G, Acc, L::P, L::W, L::N>(it, cur, um, x0, z0, tid, Lm, U, C);
     __syncthreads();
     if (ix < nx) {
 #pragma unroll
@@ -1299,23 +1335,20 @@ __device__ void tile_adjoint4(const Item<T, Acc>& it, const Step& st, int tile_x
                 const int kk = (ez + 3) * L::W + threadIdx.x + 3;
                 const int64_t x = (int64_t)iz * nx + ix;
                 Vec<T, G> Lw = vzero<T, G>(), Lu = vzero<T, G>();
-                lap4_axis<T, G, true>(Lm, C, kk, 1, Lw);
-                lap4_axis<T, G, true>(Lm, C, kk, L::W, Lw);
-                lap4_axis<T, G, false>(U, C, kk, 1, Lu);
-                lap4_axis<T, G, false>(U, C, kk, L::W, Lu);
+                Acc sb = Acc(0);
+                adj4_axis<T, G, Acc>(Lm, U, C, kk, 1, ix, nx, Lw, Lu, sb);
+                adj4_axis<T, G, Acc>(Lm, U, C, kk, L::W, iz, nz, Lw, Lu, sb);
                 T a, b;
                 damp_coeffs<T>(exd + ezd[k], a, b);
                 const Vec<T, G> l0 = Lm[kk];
                 Vec<T, G> r;
-                Acc sk = Acc(0), sb = Acc(0);
+                Acc sk = Acc(0);
 #pragma unroll
                 for (int g = 0; g < G; ++g) {
 #pragma clang fp contract(off)
                     r.v[g] = fma(a, l0.v[g], fma(b, lp[k].v[g], Lw.v[g]));
                     sk += Acc(l0.v[g] * Lu.v[g]);
                 }
-                image4_axis<T, G, Acc>(U, Lm, C, kk, 1, ix, nx, sb);
-                image4_axis<T, G, Acc>(U, Lm, C, kk, L::W, iz, nz, sb);
                 vstore<T, G>(out, x, r);
                 stg(accK, x, sK[k] + sk);
                 stg(accB, x, sB[k] + sb);
