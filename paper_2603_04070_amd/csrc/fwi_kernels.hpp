@@ -603,8 +603,9 @@ struct Lds2 {
     static constexpr int P1 = (N1 + kBlock - 1) / kBlock;
     static constexpr int ND = W0 + H0;                                  // damping: columns, then rows
     static_assert(ND <= kBlock, "one damping value per thread");
-    // F0[N0] fields, C0[N0][2] coefficients, F1[N1] fields (adjoint: also
-    // UA[N1], UB[N1]), then D[ND] damping values of the grown tile
+    // F0[N0] fields, Q0[N0] and B0[N0] coefficients (separate arrays: unit-stride
+    // neighbour reads), F1[N1] fields (adjoint: also UA[N1], UB[N1]), then D[ND]
+    // damping values of the grown tile
     static constexpr size_t bytes =
         ((size_t)N0 * (G + 2) + (size_t)N1 * G * (ADJ ? 3 : 1) + (size_t)ND) * sizeof(T);
 };
@@ -653,8 +654,9 @@ __device__ void tile_forward2(const Item<T, Acc>& it, const Step& st, int tile_x
     static_assert(NR <= kBlock, "one ring cell per thread");
     const int nx = it.nx, nz = it.nz, n = st.n;
     Vec<T, G>* U0 = reinterpret_cast<Vec<T, G>*>(smem);                  // u^n, tile + 2
-    T* C0 = reinterpret_cast<T*>(U0 + L::N0);                            // (q, bt), tile + 2
-    Vec<T, G>* U1 = reinterpret_cast<Vec<T, G>*>(C0 + 2 * L::N0);        // u^{n+1}, tile + 1
+    T* Q0 = reinterpret_cast<T*>(U0 + L::N0);                            // q, tile + 2
+    T* B0 = Q0 + L::N0;                                                  // bt, tile + 2
+    Vec<T, G>* U1 = reinterpret_cast<Vec<T, G>*>(B0 + L::N0);        // u^{n+1}, tile + 1
     T* D = reinterpret_cast<T*>(U1 + L::N1);                             // damping
     const T* cur = fwd_plane(it, st, n);
     const T* vin = vel_in(it, st, n);
@@ -712,8 +714,8 @@ __device__ void tile_forward2(const Item<T, Acc>& it, const Step& st, int tile_x
         const int c = tid + i * kBlock;
         if (c < L::N0) {
             U0[c] = f0[i];
-            C0[2 * c] = q0[i];
-            C0[2 * c + 1] = b0[i];
+            Q0[c] = q0[i];
+            B0[c] = b0[i];
         }
     }
     if (tid < L::ND) D[tid] = dmp;
@@ -725,10 +727,10 @@ __device__ void tile_forward2(const Item<T, Acc>& it, const Step& st, int tile_x
         const int k = (ez + 1) * L::W0 + ex + 1;
         const int64_t x = (int64_t)gz * nx + gx;
         T fw, fe, fn, fs, nb, c2;
-        faces<T>(gx > 0, gx < nx - 1, gz > 0, gz < nz - 1, C0[2 * k + 1], C0[2 * (k - 1) + 1],
-                 C0[2 * (k + 1) + 1], C0[2 * (k - L::W0) + 1], C0[2 * (k + L::W0) + 1], fw, fe, fn, fs);
+        faces<T>(gx > 0, gx < nx - 1, gz > 0, gz < nz - 1, B0[k], B0[k - 1],
+                 B0[k + 1], B0[k - L::W0], B0[k + L::W0], fw, fe, fn, fs);
         damp_inc<T>(D[ex + 1] + D[L::W0 + ez + 1], nb, c2);
-        const T q = C0[2 * k];
+        const T q = Q0[k];
         const Vec<T, G> u0 = U0[k], uw = U0[k - 1], ue = U0[k + 1], un = U0[k - L::W0], us = U0[k + L::W0];
         Vec<T, G> r;
 #pragma unroll
@@ -772,10 +774,10 @@ __device__ void tile_forward2(const Item<T, Acc>& it, const Step& st, int tile_x
                 const int k0 = (ez + 2) * L::W0 + threadIdx.x + 2;
                 const int64_t x = (int64_t)iz * nx + ix;
                 T fw, fe, fn, fs, nb, c2;
-                faces<T>(ix > 0, ix < nx - 1, iz > 0, iz < nz - 1, C0[2 * k0 + 1], C0[2 * (k0 - 1) + 1],
-                         C0[2 * (k0 + 1) + 1], C0[2 * (k0 - L::W0) + 1], C0[2 * (k0 + L::W0) + 1], fw, fe, fn, fs);
+                faces<T>(ix > 0, ix < nx - 1, iz > 0, iz < nz - 1, B0[k0], B0[k0 - 1],
+                         B0[k0 + 1], B0[k0 - L::W0], B0[k0 + L::W0], fw, fe, fn, fs);
                 damp_inc<T>(exd + D[L::W0 + ez + 2], nb, c2);
-                const T q = C0[2 * k0];
+                const T q = Q0[k0];
                 const Vec<T, G> u0 = U1[k1], uw = U1[k1 - 1], ue = U1[k1 + 1], un = U1[k1 - L::W1],
                                 us = U1[k1 + L::W1];
                 Vec<T, G> r, rv;
@@ -805,8 +807,9 @@ __device__ void tile_adjoint2(const Item<T, Acc>& it, const Step& st, int tile_x
     const int nx = it.nx, nz = it.nz, t = st.n, nl = it.nlam;
     const int64_t P = it.plane, ncell = (int64_t)nx * nz;
     Vec<T, G>* L0 = reinterpret_cast<Vec<T, G>*>(smem);                  // lam^t, tile + 2
-    T* C0 = reinterpret_cast<T*>(L0 + L::N0);                            // (q, bt), tile + 2
-    Vec<T, G>* L1 = reinterpret_cast<Vec<T, G>*>(C0 + 2 * L::N0);        // lam^{t-1}, tile + 1
+    T* Q0 = reinterpret_cast<T*>(L0 + L::N0);                            // q, tile + 2
+    T* B0 = Q0 + L::N0;                                                  // bt, tile + 2
+    Vec<T, G>* L1 = reinterpret_cast<Vec<T, G>*>(B0 + L::N0);        // lam^{t-1}, tile + 1
     Vec<T, G>* UA = L1 + L::N1;                                          // u^{t-1}, tile + 1
     Vec<T, G>* UB = UA + L::N1;                                          // u^{t-2}, tile + 1
     T* D = reinterpret_cast<T*>(UB + L::N1);                             // damping
@@ -869,8 +872,8 @@ __device__ void tile_adjoint2(const Item<T, Acc>& it, const Step& st, int tile_x
         const int c = tid + i * kBlock;
         if (c < L::N0) {
             L0[c] = f0[i];
-            C0[2 * c] = q0[i];
-            C0[2 * c + 1] = b0[i];
+            Q0[c] = q0[i];
+            B0[c] = b0[i];
         }
     }
 #pragma unroll
@@ -894,11 +897,11 @@ __device__ void tile_adjoint2(const Item<T, Acc>& it, const Step& st, int tile_x
             if (ix1 >= 0 && ix1 < nx && iz1 >= 0 && iz1 < nz) {
                 const int k = (ez + 1) * L::W0 + ex + 1;
                 T fw, fe, fn, fs, a, b;
-                faces<T>(ix1 > 0, ix1 < nx - 1, iz1 > 0, iz1 < nz - 1, C0[2 * k + 1], C0[2 * (k - 1) + 1],
-                         C0[2 * (k + 1) + 1], C0[2 * (k - L::W0) + 1], C0[2 * (k + L::W0) + 1], fw, fe, fn, fs);
+                faces<T>(ix1 > 0, ix1 < nx - 1, iz1 > 0, iz1 < nz - 1, B0[k], B0[k - 1],
+                         B0[k + 1], B0[k - L::W0], B0[k + L::W0], fw, fe, fn, fs);
                 damp_coeffs<T>(D[ex + 1] + D[L::W0 + ez + 1], a, b);
-                const T qc = C0[2 * k], qw = C0[2 * (k - 1)], qe = C0[2 * (k + 1)], qn = C0[2 * (k - L::W0)],
-                        qs = C0[2 * (k + L::W0)];
+                const T qc = Q0[k], qw = Q0[k - 1], qe = Q0[k + 1], qn = Q0[k - L::W0],
+                        qs = Q0[k + L::W0];
                 const Vec<T, G> l0 = L0[k], lw = L0[k - 1], le = L0[k + 1], ln = L0[k - L::W0], ls = L0[k + L::W0];
 #pragma unroll
                 for (int g = 0; g < G; ++g)
@@ -939,12 +942,12 @@ __device__ void tile_adjoint2(const Item<T, Acc>& it, const Step& st, int tile_x
                 const int64_t x = (int64_t)iz * nx + ix;
                 const bool hn = iz > 0, hs = iz < nz - 1;
                 T fw, fe, fn, fs, a, b;
-                faces<T>(hw, he, hn, hs, C0[2 * k0 + 1], C0[2 * (k0 - 1) + 1], C0[2 * (k0 + 1) + 1],
-                         C0[2 * (k0 - L::W0) + 1], C0[2 * (k0 + L::W0) + 1], fw, fe, fn, fs);
+                faces<T>(hw, he, hn, hs, B0[k0], B0[k0 - 1], B0[k0 + 1],
+                         B0[k0 - L::W0], B0[k0 + L::W0], fw, fe, fn, fs);
                 const T cn = hn ? hf : T(1), cs = hs ? hf : T(1);
                 damp_coeffs<T>(exd + D[L::W0 + ez + 2], a, b);
-                const T qc = C0[2 * k0], qw = C0[2 * (k0 - 1)], qe = C0[2 * (k0 + 1)], qn = C0[2 * (k0 - L::W0)],
-                        qs = C0[2 * (k0 + L::W0)];
+                const T qc = Q0[k0], qw = Q0[k0 - 1], qe = Q0[k0 + 1], qn = Q0[k0 - L::W0],
+                        qs = Q0[k0 + L::W0];
                 const Vec<T, G> l0 = L0[k0], lw = L0[k0 - 1], le = L0[k0 + 1], ln = L0[k0 - L::W0],
                                 ls = L0[k0 + L::W0];
                 const Vec<T, G> m0 = L1[k1], mw = L1[k1 - 1], me = L1[k1 + 1], mn = L1[k1 - L::W1],
