@@ -292,6 +292,9 @@ def main():
     cpu = None
     if args.cpu_baseline:
         cpu = run_cpu_baseline(media, args)
+        # the same oracle on one core, on a sample sized for ~10 s
+        one = run_cpu_baseline(media, args, threads=1, seconds=10.0)
+        cpu["single_core"] = {k: one[k] for k in ("value", "cores", "seconds", "sample")}
         progress("oracle baseline timed")
 
     # the committed counter runs measured the second-order kernels
@@ -345,15 +348,17 @@ def main():
     print(json.dumps(line))
 
 
-def run_cpu_baseline(media, args):
+def run_cpu_baseline(media, args, threads=0, seconds=15.0):
     import numpy as np
     import oracle
     m = media[0]
     g = m.geom
-    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or (os.cpu_count() or 1)
-    # ~15 s at the oracle's measured ~0.0175 G updates/s per thread: as many
-    # transmits as the full schedule allows, else the first steps of two
-    budget_updates = 15.0 * 0.0175e9 * min(threads, 16)
+    if threads <= 0:
+        threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or (os.cpu_count() or 1)
+    # ~`seconds` at the oracle's measured rate (~0.17 G updates/s on one core,
+    # ~0.28 on 16: it parallelises rows within a step): as many transmits as
+    # the full schedule allows, else the first steps of two
+    budget_updates = seconds * (0.17e9 if threads == 1 else 0.28e9)
     ntx = int(min(g.n_tx, max(2, budget_updates // (2 * g.nx * g.nz * g.nt))))
     steps = args.cpu_steps
     if steps <= 0:
