@@ -17,7 +17,8 @@
 //
 // One launch advances every active item by one step of its own schedule:
 //   FWD     u^{n+1} = a u^n + beta u^{n-1} + Q L u^n, + w[n] at the source,
-//           traces d[n] = u^{n+1}[rcv]                        (eq. 2-3)
+//           traces d[n] = u^{n+1}[rcv]                        (eq. 2-3),
+//           evaluated in increment form (v = u^n - u^{n-1} carried, below)
 //   RECOMP  the same update without sampling, re-running a checkpointed
 //           segment into the segment buffer
 //   ADJ     lam^{t-1} = a lam^t + L(Q lam^t) + beta lam^{t+1} + s[t-2] at rcv,
@@ -174,20 +175,22 @@ struct Step {
 // last segment's adjoint steps, then per earlier segment its recompute and
 // its adjoint steps, each run cut into launches of S steps (the last one of a
 // run may be shorter).
-__device__ __forceinline__ Step decode(int T, int K, int J, int s, int S)
+__host__ __device__ inline int imin(int x, int y) { return x < y ? x : y; }
+
+__host__ __device__ inline Step decode(int T, int K, int J, int s, int S)
 {
     Step r{kIdle, 0, 0, 0};
     if (s < 0) return r;
     const int nf = (T + S - 1) / S;
     if (s < nf) {
-        r.phase = kFwd; r.n = s * S; r.j = r.n / K; r.count = min(S, T - r.n);
+        r.phase = kFwd; r.n = s * S; r.j = r.n / K; r.count = imin(S, T - r.n);
         return r;
     }
     s -= nf;
     const int last = T - (J - 1) * K;
     const int nl = (last + S - 1) / S;
     if (s < nl) {
-        r.phase = kAdj; r.n = T + 1 - s * S; r.j = J - 1; r.count = min(S, last - s * S);
+        r.phase = kAdj; r.n = T + 1 - s * S; r.j = J - 1; r.count = imin(S, last - s * S);
         return r;
     }
     s -= nl;
@@ -196,10 +199,10 @@ __device__ __forceinline__ Step decode(int T, int K, int J, int s, int S)
         const int blk = s / (2 * nk), rem = s - blk * 2 * nk;
         r.j = J - 2 - blk;
         if (rem < nk) {
-            r.phase = kRecomp; r.n = r.j * K + rem * S; r.count = min(S, K - rem * S);
+            r.phase = kRecomp; r.n = r.j * K + rem * S; r.count = imin(S, K - rem * S);
         } else {
             const int m = rem - nk;
-            r.phase = kAdj; r.n = r.j * K + K + 1 - m * S; r.count = min(S, K - m * S);
+            r.phase = kAdj; r.n = r.j * K + K + 1 - m * S; r.count = imin(S, K - m * S);
         }
     }
     return r;
