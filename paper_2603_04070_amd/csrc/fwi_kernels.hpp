@@ -1402,23 +1402,30 @@ __global__ __launch_bounds__(kBlock) void adj4_kernel(const Item<T, Acc>* __rest
 // word, every workgroup then leaves, and the host reports the failure.
 
 // bar[0]: arrivals, bar[1]: generation, bar[2]: abort.
+// One agent-scope release fence per workgroup before it arrives (its stores,
+// and those of the workgroup's other waves ordered by the workgroup barrier,
+// written back from this XCD's L2) and one agent-scope acquire fence after
+// the generation moved (stale lines of this XCD's caches invalidated); the
+// counter and the flag are relaxed atomics, except the last arrival's
+// release of the new generation.  Each fence costs a pass over the XCD's L2,
+// so there is one of each per workgroup.
 __device__ __forceinline__ bool grid_sync(unsigned* bar, unsigned nblocks, unsigned spin_limit)
 {
     __shared__ unsigned ok;
     __syncthreads();
     if (threadIdx.x == 0 && threadIdx.y == 0) {
         bool good = true;
-        const unsigned g = __hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-        __threadfence();
-        const unsigned a = __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        // the generation cannot move before this workgroup arrives
+        const unsigned g = __hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        const unsigned a = __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (a + 1 == nblocks) {
+            // the reset of the counter is released with the new generation
+            // (acquired by the waiting workgroups' fence below)
             __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __hip_atomic_fetch_add(&bar[1], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         } else {
             unsigned polls = 0;
-            // relaxed polls (an acquire per poll would invalidate this XCD's L2 each
-            // time under the feet of workgroups still computing); the fence below
-            // is the acquire
             while (__hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g) {
                 if (__hip_atomic_load(&bar[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u ||
                     ++polls > spin_limit) {
@@ -1429,7 +1436,7 @@ __device__ __forceinline__ bool grid_sync(unsigned* bar, unsigned nblocks, unsig
                 __builtin_amdgcn_s_sleep(2);
             }
         }
-        __threadfence();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         ok = good ? 1u : 0u;
     }
     __syncthreads();
