@@ -607,10 +607,13 @@ struct Lds2 {
     static constexpr int ND = W0 + H0;                                  // damping: columns, then rows
     static_assert(ND <= kBlock, "one damping value per thread");
     // F0[N0] fields, Q0[N0] and B0[N0] coefficients (separate arrays: unit-stride
-    // neighbour reads), F1[N1] fields (adjoint: also UA[N1], UB[N1]), then D[ND]
-    // damping values of the grown tile
+    // neighbour reads), then the tile + 1 field planes: F1[N1] (forward), or
+    // (adjoint) two planes without their first and last cells, the top-left and
+    // bottom-right corners that no tile cell reads; then D[ND] damping values
+    // of the grown tile.  For FP32 and four transmits the adjoint takes exactly
+    // 40 KiB, so four workgroups share a CU's 160 KiB.
     static constexpr size_t bytes =
-        ((size_t)N0 * (G + 2) + (size_t)N1 * G * (ADJ ? 3 : 1) + (size_t)ND) * sizeof(T);
+        ((size_t)N0 * (G + 2) + (ADJ ? (size_t)(N1 - 2) * G * 2 : (size_t)N1 * G) + (size_t)ND) * sizeof(T);
 };
 
 template <typename T, int G, int R, bool ADJ>
@@ -812,10 +815,11 @@ __device__ void tile_adjoint2(const Item<T, Acc>& it, const Step& st, int tile_x
     Vec<T, G>* L0 = reinterpret_cast<Vec<T, G>*>(smem);                  // lam^t, tile + 2
     T* Q0 = reinterpret_cast<T*>(L0 + L::N0);                            // q, tile + 2
     T* B0 = Q0 + L::N0;                                                  // bt, tile + 2
-    Vec<T, G>* L1 = reinterpret_cast<Vec<T, G>*>(B0 + L::N0);        // lam^{t-1}, tile + 1
-    Vec<T, G>* UA = L1 + L::N1;                                          // u^{t-1}, tile + 1
-    Vec<T, G>* UB = UA + L::N1;                                          // u^{t-2}, tile + 1
-    T* D = reinterpret_cast<T*>(UB + L::N1);                             // damping
+    // two tile + 1 planes without their first and last (corner) cells: X holds
+    // u^{t-1} for the imaging of (lam^t, u^{t-1}), then lam^{t-1}; Y holds u^{t-2}
+    Vec<T, G>* X = reinterpret_cast<Vec<T, G>*>(B0 + L::N0) - 1;
+    Vec<T, G>* Y = X + (L::N1 - 2);
+    T* D = reinterpret_cast<T*>(Y + (L::N1 - 1));                        // damping
     const T* cur = it.lam + (int64_t)(t % nl) * P;
     const T* p1 = it.lam + (int64_t)((t + 1) % nl) * P;
     T* out1 = it.lam + (int64_t)((t - 1) % nl) * P;
@@ -882,21 +886,22 @@ __device__ void tile_adjoint2(const Item<T, Acc>& it, const Step& st, int tile_x
 #pragma unroll
     for (int i = 0; i < L::P1; ++i) {
         const int c = tid + i * kBlock;
-        if (c < L::N1) {
-            UA[c] = ua[i];
-            UB[c] = ub[i];
+        if (c > 0 && c < L::N1 - 1) {
+            X[c] = ua[i];
+            Y[c] = ub[i];
         }
     }
     if (tid < L::ND) D[tid] = dmp;
     __syncthreads();
-    // lam^{t-1} on the tile grown by one cell
+    // lam^{t-1} on the tile grown by one cell, into registers until X is free
+    Vec<T, G> m1[L::P1];
 #pragma unroll
     for (int i = 0; i < L::P1; ++i) {
         const int c = tid + i * kBlock;
+        m1[i] = vzero<T, G>();
         if (c < L::N1) {
             const int ex = c % L::W1, ez = c / L::W1;
             const int ix1 = x0 - 1 + ex, iz1 = z0 - 1 + ez;
-            Vec<T, G> r = vzero<T, G>();
             if (ix1 >= 0 && ix1 < nx && iz1 >= 0 && iz1 < nz) {
                 const int k = (ez + 1) * L::W0 + ex + 1;
                 T fw, fe, fn, fs, a, b;
@@ -908,34 +913,67 @@ __device__ void tile_adjoint2(const Item<T, Acc>& it, const Step& st, int tile_x
                 const Vec<T, G> l0 = L0[k], lw = L0[k - 1], le = L0[k + 1], ln = L0[k - L::W0], ls = L0[k + L::W0];
 #pragma unroll
                 for (int g = 0; g < G; ++g)
-                    r.v[g] = adj_cell<T>(a, b, fw, fe, fn, fs, qc * l0.v[g], qw * lw.v[g], qe * le.v[g],
-                                         qn * ln.v[g], qs * ls.v[g], l0.v[g], pv[i].v[g]);
+                    m1[i].v[g] = adj_cell<T>(a, b, fw, fe, fn, fs, qc * l0.v[g], qw * lw.v[g], qe * le.v[g],
+                                             qn * ln.v[g], qs * ls.v[g], l0.v[g], pv[i].v[g]);
             }
-            L1[c] = r;
         }
     }
-    // adjoint source of lam^{t-1} (sample t-2) at the receivers of the grown tile
-    {
+    // on the tile: the imaging of (lam^t, u^{t-1}), summed over the transmits
+    const bool hw = ix > 0, he = ix < nx - 1;
+    const T hf = T(0.5);
+    const T cw = hw ? hf : T(1), ce = he ? hf : T(1);
+    Acc ska[R], sba[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        const int ez = (int)threadIdx.y * R + k, iz = z0 + ez;
+        ska[k] = Acc(0);
+        sba[k] = Acc(0);
+        if (ix < nx && iz < nz) {
+            const int k1 = (ez + 1) * L::W1 + threadIdx.x + 1;
+            const int k0 = (ez + 2) * L::W0 + threadIdx.x + 2;
+            const bool hn = iz > 0, hs = iz < nz - 1;
+            T fw, fe, fn, fs;
+            faces<T>(hw, he, hn, hs, B0[k0], B0[k0 - 1], B0[k0 + 1], B0[k0 - L::W0], B0[k0 + L::W0], fw, fe, fn, fs);
+            const T cn = hn ? hf : T(1), cs = hs ? hf : T(1);
+            const T qc = Q0[k0], qw = Q0[k0 - 1], qe = Q0[k0 + 1], qn = Q0[k0 - L::W0], qs = Q0[k0 + L::W0];
+            const Vec<T, G> l0 = L0[k0], lw = L0[k0 - 1], le = L0[k0 + 1], ln = L0[k0 - L::W0],
+                            ls = L0[k0 + L::W0];
+            const Vec<T, G> a0 = X[k1], aw = X[k1 - 1], ae = X[k1 + 1], an = X[k1 - L::W1], as = X[k1 + L::W1];
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                T k1a, b1a;
+                image_cell<T>(fw, fe, fn, fs, cw, ce, cn, cs, l0.v[g], qc * l0.v[g], qw * lw.v[g], qe * le.v[g],
+                              qn * ln.v[g], qs * ls.v[g], a0.v[g], aw.v[g], ae.v[g], an.v[g], as.v[g], k1a, b1a);
+                ska[k] += Acc(k1a);
+                sba[k] += Acc(b1a);
+            }
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < L::P1; ++i) {
+        const int c = tid + i * kBlock;
+        if (c > 0 && c < L::N1 - 1) X[c] = m1[i];
+    }
+    __syncthreads();
+    // adjoint source of lam^{t-1} (sample t-2) at the receivers of the grown
+    // tile (the two corner cells that X does not hold are read by no tile cell)
+    if (rcv_x.e1 > rcv_x.e0 && has_adj_source(it)) {
+        for (int e = rcv_x.e0 + tid; e < rcv_x.e1; e += kBlock) {
+            const Entry en = ld_entry(it.entries_x, e);
+            if (en.run == 0) continue;
+            T sum = T(0);
+            for (int k = 0; k < en.run; ++k) sum += adj_source(it, ld_entry(it.entries_x, e + k), t - 2);
+            const int cell = en.slot / G, g = en.slot - cell * G;
+            const int ex = cell % nx - (x0 - 1), ez = cell / nx - (z0 - 1);
+            const int c = ez * L::W1 + ex;
+            if (c > 0 && c < L::N1 - 1) X[c].v[g] += sum;
+        }
         __syncthreads();
-        if (rcv_x.e1 > rcv_x.e0 && has_adj_source(it)) {
-            for (int e = rcv_x.e0 + tid; e < rcv_x.e1; e += kBlock) {
-                const Entry en = ld_entry(it.entries_x, e);
-                if (en.run == 0) continue;
-                T sum = T(0);
-                for (int k = 0; k < en.run; ++k) sum += adj_source(it, ld_entry(it.entries_x, e + k), t - 2);
-                const int cell = en.slot / G, g = en.slot - cell * G;
-                const int ex = cell % nx - (x0 - 1), ez = cell / nx - (z0 - 1);
-                L1[ez * L::W1 + ex].v[g] += sum;
-            }
-            __syncthreads();
-        }
     }
-    // on the tile: imaging of (lam^t, u^{t-1}), lam^{t-2}, imaging of (lam^{t-1}, u^{t-2})
+    // on the tile: lam^{t-2}, the imaging of (lam^{t-1}, u^{t-2})
     if (ix < nx) {
         const T exd = D[threadIdx.x + 2];
-        const bool hw = ix > 0, he = ix < nx - 1;
-        const T hf = T(0.5);
-        const T cw = hw ? hf : T(1), ce = he ? hf : T(1);
 #pragma unroll
         for (int k = 0; k < R; ++k) {
             const int ez = (int)threadIdx.y * R + k, iz = z0 + ez;
@@ -951,40 +989,31 @@ __device__ void tile_adjoint2(const Item<T, Acc>& it, const Step& st, int tile_x
                 damp_coeffs<T>(exd + D[L::W0 + ez + 2], a, b);
                 const T qc = Q0[k0], qw = Q0[k0 - 1], qe = Q0[k0 + 1], qn = Q0[k0 - L::W0],
                         qs = Q0[k0 + L::W0];
-                const Vec<T, G> l0 = L0[k0], lw = L0[k0 - 1], le = L0[k0 + 1], ln = L0[k0 - L::W0],
-                                ls = L0[k0 + L::W0];
-                const Vec<T, G> m0 = L1[k1], mw = L1[k1 - 1], me = L1[k1 + 1], mn = L1[k1 - L::W1],
-                                ms = L1[k1 + L::W1];
-                const Vec<T, G> a0 = UA[k1], aw = UA[k1 - 1], ae = UA[k1 + 1], an = UA[k1 - L::W1],
-                                as = UA[k1 + L::W1];
-                const Vec<T, G> c0 = UB[k1], cw2 = UB[k1 - 1], ce2 = UB[k1 + 1], cn2 = UB[k1 - L::W1],
-                                cs2 = UB[k1 + L::W1];
+                const Vec<T, G> l0 = L0[k0];
+                const Vec<T, G> m0 = X[k1], mw = X[k1 - 1], me = X[k1 + 1], mn = X[k1 - L::W1],
+                                ms = X[k1 + L::W1];
+                const Vec<T, G> c0 = Y[k1], cw2 = Y[k1 - 1], ce2 = Y[k1 + 1], cn2 = Y[k1 - L::W1],
+                                cs2 = Y[k1 + L::W1];
                 Vec<T, G> r;
-                // the two time levels' imaging sums are added to the accumulators one
-                // after the other, exactly as two one-step launches would
-                Acc ska = Acc(0), sba = Acc(0), skb = Acc(0), sbb = Acc(0);
+                Acc skb = Acc(0), sbb = Acc(0);
 #pragma unroll
                 for (int g = 0; g < G; ++g) {
-                    const T w0 = qc * l0.v[g], ww = qw * lw.v[g], we = qe * le.v[g], wn = qn * ln.v[g],
-                            ws = qs * ls.v[g];
                     const T v0 = qc * m0.v[g], vw = qw * mw.v[g], ve = qe * me.v[g], vn = qn * mn.v[g],
                             vs = qs * ms.v[g];
                     r.v[g] = adj_cell<T>(a, b, fw, fe, fn, fs, v0, vw, ve, vn, vs, m0.v[g], l0.v[g]);
-                    T k1a, b1a, k1b, b1b;
-                    image_cell<T>(fw, fe, fn, fs, cw, ce, cn, cs, l0.v[g], w0, ww, we, wn, ws, a0.v[g], aw.v[g],
-                                  ae.v[g], an.v[g], as.v[g], k1a, b1a);
+                    T k1b, b1b;
                     image_cell<T>(fw, fe, fn, fs, cw, ce, cn, cs, m0.v[g], v0, vw, ve, vn, vs, c0.v[g], cw2.v[g],
                                   ce2.v[g], cn2.v[g], cs2.v[g], k1b, b1b);
-                    ska += Acc(k1a);
-                    sba += Acc(b1a);
                     skb += Acc(k1b);
                     sbb += Acc(b1b);
                 }
                 vstore<T, G>(out1, x, m0);
                 vstore<T, G>(out2, x, r);
+                // the two time levels' imaging sums are added to the accumulators one
+                // after the other, exactly as two one-step launches would
                 Acc vk = sK[k], vb = sB[k];
-                vk += ska;
-                vb += sba;
+                vk += ska[k];
+                vb += sba[k];
                 vk += skb;
                 vb += sbb;
                 stg(accK, x, vk);

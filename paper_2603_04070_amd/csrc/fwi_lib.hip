@@ -492,10 +492,11 @@ static fwi_status create_impl(fwi_plan* p, fwi_dtype dtype, const fwi_grid* grid
     // form); with an explicit rows value that two-step tiles do not support, one step
     auto two_step_ok = [&](int rows) {
         if (rows != 1 && rows != 2 && rows != 4) return false;
-        // LDS of the two-step adjoint: tile + 2 (fields, q, bt) and three tile + 1 field planes
+        // LDS of the two-step adjoint: tile + 2 (fields, q, bt) and two tile + 1
+        // field planes less their two corner cells
         const size_t n0 = (size_t)(kTileX + 4) * (kWavesZ * rows + 4), n1 = (size_t)(kTileX + 2) * (kWavesZ * rows + 2);
         const size_t ts = dtype == FWI_F64 ? 8 : 4;
-        return (n0 * (p->G + 2) + 3 * n1 * p->G) * ts <= kLdsBytes;
+        return (n0 * (p->G + 2) + 2 * (n1 - 2) * p->G) * ts <= kLdsBytes;
     };
     p->order = o.order == 4 ? 4 : 2;
     if (p->order == 4) {

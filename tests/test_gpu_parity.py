@@ -163,8 +163,6 @@ def _seam_medium(seed, nt=151, n_tx=3):
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 @pytest.mark.parametrize("ckpt,rows", [(0, 2), (9, 2), (10**6, 1), (7, 1), (5, 4)])
 def test_two_step_launches(dtype, ckpt, rows):
-    if dtype == "f64" and rows == 4:
-        pytest.skip("the FP64 two-step tile of 16 rows exceeds the LDS of a compute unit")
     m = _seam_medium(31)
     obs = _observed(m, 4)
     ref = oracle_grad(m, obs)
