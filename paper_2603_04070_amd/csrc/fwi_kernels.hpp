@@ -607,13 +607,14 @@ struct Lds2 {
     static constexpr int ND = W0 + H0;                                  // damping: columns, then rows
     static_assert(ND <= kBlock, "one damping value per thread");
     // F0[N0] fields, Q0[N0] and B0[N0] coefficients (separate arrays: unit-stride
-    // neighbour reads), then the tile + 1 field planes: F1[N1] (forward), or
-    // (adjoint) two planes without their first and last cells, the top-left and
-    // bottom-right corners that no tile cell reads; then D[ND] damping values
-    // of the grown tile.  For FP32 and four transmits the adjoint takes exactly
-    // 40 KiB, so four workgroups share a CU's 160 KiB.
+    // neighbour reads), then (adjoint only) two tile + 1 field planes without
+    // their first and last cells, the top-left and bottom-right corners that
+    // no tile cell reads; then D[ND] damping values of the grown tile.  The
+    // forward writes its tile + 1 plane over F0.  For FP32 and four transmits
+    // the adjoint takes exactly 40 KiB, so four workgroups share a CU's
+    // 160 KiB, and the forward 19.4 KiB (eight).
     static constexpr size_t bytes =
-        ((size_t)N0 * (G + 2) + (ADJ ? (size_t)(N1 - 2) * G * 2 : (size_t)N1 * G) + (size_t)ND) * sizeof(T);
+        ((size_t)N0 * (G + 2) + (ADJ ? (size_t)(N1 - 2) * G * 2 : 0) + (size_t)ND) * sizeof(T);
 };
 
 template <typename T, int G, int R, bool ADJ>
@@ -662,8 +663,8 @@ __device__ void tile_forward2(const Item<T, Acc>& it, const Step& st, int tile_x
     Vec<T, G>* U0 = reinterpret_cast<Vec<T, G>*>(smem);                  // u^n, tile + 2
     T* Q0 = reinterpret_cast<T*>(U0 + L::N0);                            // q, tile + 2
     T* B0 = Q0 + L::N0;                                                  // bt, tile + 2
-    Vec<T, G>* U1 = reinterpret_cast<Vec<T, G>*>(B0 + L::N0);        // u^{n+1}, tile + 1
-    T* D = reinterpret_cast<T*>(U1 + L::N1);                             // damping
+    Vec<T, G>* U1 = U0;                                                  // u^{n+1}, tile + 1, over u^n
+    T* D = B0 + L::N0;                                                   // damping
     const T* cur = fwd_plane(it, st, n);
     const T* vin = vel_in(it, st, n);
     T* out1 = it.seg + (int64_t)(n % it.K) * it.plane;
@@ -748,26 +749,30 @@ __device__ void tile_forward2(const Item<T, Acc>& it, const Step& st, int tile_x
         }
         return r;
     };
-    // step n: the ring (u^{n+1} to LDS only), then the tile cells of this
-    // lane, with the map of step n+1, so that v^{n+1} stays in registers
-    if (tid < NR) U1[rez * L::W1 + rex] = rin ? step1(rex, rez, rix, riz, vr) : vzero<T, G>();
+    // step n: the ring (u^{n+1} for LDS only), then the tile cells of this
+    // lane, with the map of step n+1, so that v^{n+1} stays in registers;
+    // u^{n+1} is held in registers until every lane has read u^n, then
+    // written over it
+    Vec<T, G> ur = vzero<T, G>(), ut[R];
+    if (rin) ur = step1(rex, rez, rix, riz, vr);
 #pragma unroll
     for (int k = 0; k < R; ++k) {
         const int ez = (int)threadIdx.y * R + k, iz = z0 + ez;
-        const int k1 = (ez + 1) * L::W1 + threadIdx.x + 1;
+        ut[k] = vzero<T, G>();
         if (ix < nx && iz < nz) {
-            const Vec<T, G> r = step1((int)threadIdx.x + 1, ez + 1, ix, iz, vt[k]);
+            ut[k] = step1((int)threadIdx.x + 1, ez + 1, ix, iz, vt[k]);
             const int64_t x = (int64_t)iz * nx + ix;
-            if (keep1) vstore<T, G>(out1, x, r);
+            if (keep1) vstore<T, G>(out1, x, ut[k]);
             if (ck1) {
                 vstore<T, G>(ck1, x, vt[k]);
-                vstore<T, G>(ck1 + it.plane, x, r);
+                vstore<T, G>(ck1 + it.plane, x, ut[k]);
             }
-            U1[k1] = r;
-        } else {
-            U1[k1] = vzero<T, G>();
         }
     }
+    __syncthreads();
+    if (tid < NR) U1[rez * L::W1 + rex] = ur;
+#pragma unroll
+    for (int k = 0; k < R; ++k) U1[((int)threadIdx.y * R + k + 1) * L::W1 + threadIdx.x + 1] = ut[k];
     __syncthreads();
     // step n+1 on the tile
     if (ix < nx) {
