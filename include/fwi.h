@@ -64,7 +64,8 @@ typedef enum fwi_mode {
 /* One medium's grid and acquisition geometry (Sec. II-A: one transmitter per
  * shot, a receiver subset per shot).  Host data, copied by fwi_plan_create. */
 typedef struct fwi_grid {
-    int32_t nx, nz;          /* cells; each >= 2 * npml + 3                                     */
+    int32_t nx, nz;          /* cells; each >= 2 * npml + 3; nx*nz*max(group,2)*sizeof(dtype)   */
+                             /* below 4 GiB (FWI_ERR_INVALID otherwise)                         */
     int32_t nt;              /* time steps = samples per trace, >= 1                            */
     int32_t npml;            /* absorbing-layer width in cells, >= 0                            */
     double h;                /* grid spacing (m), > 0                                           */
@@ -103,9 +104,12 @@ typedef struct fwi_options {
     int32_t use_graph;       /* 1: record the batched launch sequence once in a hipGraph and     */
                              /*    replay it (FWI_BATCHED only)                                  */
     int32_t acc_double;      /* 1: imaging accumulators in double for FWI_F32 (default 0)       */
-    int32_t steps_per_launch;/* time steps fused per launch: 0 = default (2 batched, 1 plain),    */
-                             /*    1 or 2; 2 falls back to 1 when a wrapping segment buffer has  */
-                             /*    K < 4; with 2, rows must be 1, 2 or 4 (FP64: 1 or 2)           */
+    int32_t steps_per_launch;/* forward-type time steps fused per launch: 0 = default (3 batched, */
+                             /*    2 persistent, 1 plain), 1, 2 or 3.  Adjoint launches fuse     */
+                             /*    min(this, 2) steps.  3 falls back to 2 when a replayed item's */
+                             /*    K is not a multiple of 3 (the automatic K is a multiple of 6); */
+                             /*    2 or 3 fall back to 1 when a wrapping segment buffer has K < 4; */
+                             /*    with 2 or 3, rows must be 1, 2 or 4; 3 is not persistent      */
     int32_t forward_only;    /* 1: traces and misfit only; no replay state is kept and           */
                              /*    gradient or adjoint calls return FWI_ERR_INVALID              */
     int32_t persistent;      /* 1: one launch per wave runs every step, its workgroups meeting   */
@@ -135,7 +139,7 @@ typedef struct fwi_plan_info {
     int32_t max_ckpt;        /* largest K over items (nt when every plane is kept)              */
     int32_t min_ckpt;
     int32_t waves;           /* groups of items run one after another to fit the memory budget */
-    int32_t steps_per_launch;/* time steps fused per launch actually used                       */
+    int32_t steps_per_launch;/* forward-type time steps fused per launch actually used          */
 } fwi_plan_info;
 
 /* Validate the geometry and options, copy the geometry, build the device

@@ -87,6 +87,8 @@ class Plan:
     (one transmit and one step per launch).  ``ckpt``: checkpoint interval K
     (0 = automatic, >= nt keeps every plane).  ``group``: transmits per work
     item (0 = automatic).  ``rows``: rows per thread of a 64 x 4*rows tile.
+    ``steps_per_launch``: forward-type steps fused per launch (0 =
+    automatic: 3 batched, 1 plain; adjoint launches fuse at most 2).
     ``order``: 2 (the 5-point flux form) or 4 (staggered fourth-order
     differences, one step per launch).
     """

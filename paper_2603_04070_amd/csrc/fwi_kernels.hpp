@@ -59,8 +59,8 @@ struct Item {
     int32_t nx, nz, nt, g_used;      // g_used <= G real transmits
     int32_t K, J, tiles_x, n_tiles;
     int32_t n_rcv, tx0, inject_adj, sample;   // inject_adj: 1 if d_adj drives the adjoint
-    int32_t S, nlam;                 // steps fused per launch; lambda planes (lam^tau in tau mod nlam)
-    int32_t keep_from, pad1;         // first level the adjoint reads from the first forward pass
+    int32_t S, nlam;                 // forward-type steps fused per launch; lambda planes (lam^tau in tau mod nlam)
+    int32_t keep_from, Sa;           // first level the adjoint reads from the first forward pass; adjoint steps per launch
     int64_t plane;                   // elements per field plane = nx*nz*G
     int64_t wavelet_stride;
     const T* coef;                   // [nz*nx] x (Q, bt)
@@ -145,6 +145,56 @@ __device__ __forceinline__ void vstore(T* p, int64_t cell, const Vec<T, G>& v)
     *(N __attribute__((address_space(1)))*)(p + cell * G) = n;
 }
 
+// The same accesses with a 32-bit element index into a plane whose base is
+// uniform across the workgroup: the byte offset is formed in 32 bits, so the
+// access takes the scalar-base form (64-bit base in SGPRs, 32-bit offset per
+// lane) instead of 64-bit address arithmetic in every lane.  Plans keep every
+// plane and coefficient array below 4 GiB, so the offsets cannot wrap.
+template <typename T>
+__device__ __forceinline__ T ldg32(const T* p, uint32_t i)
+{
+    using B = const char __attribute__((address_space(1)))*;
+    return *(const T __attribute__((address_space(1)))*)((B)p + i * (uint32_t)sizeof(T));
+}
+
+template <typename T>
+__device__ __forceinline__ void stg32(T* p, uint32_t i, T v)
+{
+    using B = char __attribute__((address_space(1)))*;
+    *(T __attribute__((address_space(1)))*)((B)p + i * (uint32_t)sizeof(T)) = v;
+}
+
+template <typename T, int G>
+__device__ __forceinline__ Vec<T, G> vload32(const T* p, uint32_t cell)
+{
+    using N = typename Native<T, G>::type;
+    using B = const char __attribute__((address_space(1)))*;
+    const N n = *(const N __attribute__((address_space(1)))*)((B)p + cell * (uint32_t)(sizeof(T) * G));
+    Vec<T, G> r;
+    if constexpr (G == 1) {
+        r.v[0] = n;
+    } else {
+#pragma unroll
+        for (int g = 0; g < G; ++g) r.v[g] = n[g];
+    }
+    return r;
+}
+
+template <typename T, int G>
+__device__ __forceinline__ void vstore32(T* p, uint32_t cell, const Vec<T, G>& v)
+{
+    using N = typename Native<T, G>::type;
+    using B = char __attribute__((address_space(1)))*;
+    N n;
+    if constexpr (G == 1) {
+        n = v.v[0];
+    } else {
+#pragma unroll
+        for (int g = 0; g < G; ++g) n[g] = v.v[g];
+    }
+    *(N __attribute__((address_space(1)))*)((B)p + cell * (uint32_t)(sizeof(T) * G)) = n;
+}
+
 template <typename T, int G>
 __device__ __forceinline__ Vec<T, G> vzero()
 {
@@ -171,13 +221,14 @@ struct Step {
 };
 
 // Position of an item with (T, K, J) at launch s of its schedule, with up to
-// S steps of one phase fused per launch: forward steps in runs of S, then the
-// last segment's adjoint steps, then per earlier segment its recompute and
-// its adjoint steps, each run cut into launches of S steps (the last one of a
-// run may be shorter).
+// S forward-type steps (first pass, recompute) or Sa adjoint steps fused per
+// launch: forward steps in runs of S, then the last segment's adjoint steps,
+// then per earlier segment its recompute and its adjoint steps, each run cut
+// into launches of S (forward-type) or Sa (adjoint) steps, the last launch of
+// a run possibly shorter.
 __host__ __device__ inline int imin(int x, int y) { return x < y ? x : y; }
 
-__host__ __device__ inline Step decode(int T, int K, int J, int s, int S)
+__host__ __device__ inline Step decode(int T, int K, int J, int s, int S, int Sa)
 {
     Step r{kIdle, 0, 0, 0};
     if (s < 0) return r;
@@ -188,21 +239,21 @@ __host__ __device__ inline Step decode(int T, int K, int J, int s, int S)
     }
     s -= nf;
     const int last = T - (J - 1) * K;
-    const int nl = (last + S - 1) / S;
+    const int nl = (last + Sa - 1) / Sa;
     if (s < nl) {
-        r.phase = kAdj; r.n = T + 1 - s * S; r.j = J - 1; r.count = imin(S, last - s * S);
+        r.phase = kAdj; r.n = T + 1 - s * Sa; r.j = J - 1; r.count = imin(Sa, last - s * Sa);
         return r;
     }
     s -= nl;
-    const int nk = (K + S - 1) / S;
-    if (s < 2 * nk * (J - 1)) {
-        const int blk = s / (2 * nk), rem = s - blk * 2 * nk;
+    const int nkf = (K + S - 1) / S, nka = (K + Sa - 1) / Sa, nb = nkf + nka;
+    if (s < nb * (J - 1)) {
+        const int blk = s / nb, rem = s - blk * nb;
         r.j = J - 2 - blk;
-        if (rem < nk) {
+        if (rem < nkf) {
             r.phase = kRecomp; r.n = r.j * K + rem * S; r.count = imin(S, K - rem * S);
         } else {
-            const int m = rem - nk;
-            r.phase = kAdj; r.n = r.j * K + K + 1 - m * S; r.count = imin(S, K - m * S);
+            const int m = rem - nkf;
+            r.phase = kAdj; r.n = r.j * K + K + 1 - m * Sa; r.count = imin(Sa, K - m * Sa);
         }
     }
     return r;
@@ -316,22 +367,33 @@ __device__ __forceinline__ const T* fwd_plane(const Item<T, Acc>& it, const Step
     return it.seg + (int64_t)((tau - 1) % it.K) * it.plane;
 }
 
+// v slot of level tau.  A launch of two or more steps reads v^n at other
+// tiles' cells, so it must write v^{n+c} to the other slot.  With at most two
+// steps per launch, slot floor(tau/2) mod 2: a two-step launch starts at an
+// even level (K is even).  With three, slot ceil(tau/3) mod 2: launches start
+// at multiples of 3 (K is a multiple of 3), so a launch of 2 or 3 steps flips
+// the slot.  A one-step launch reads and writes each cell's own value, in
+// place or across slots.
+template <typename T, typename Acc>
+__device__ __forceinline__ int vel_slot(const Item<T, Acc>& it, int tau)
+{
+    return it.S == 3 ? ((tau + 2) / 3) & 1 : (tau >> 1) & 1;
+}
+
 // Plane of v^tau read by a forward-type step: zero for tau = 0; on
-// recompute, the checkpoint of segment j for tau = jK; else its v slot.  A
-// two-step launch reads slot(n) and writes slot(n+2), which always differ; a
-// one-step launch reads and writes one cell's value in place or across slots.
+// recompute, the checkpoint of segment j for tau = jK; else its v slot.
 template <typename T, typename Acc>
 __device__ __forceinline__ const T* vel_in(const Item<T, Acc>& it, const Step& st, int tau)
 {
     if (tau <= 0) return it.zero;
     if (st.phase == kRecomp && tau == st.j * it.K) return it.ck + (int64_t)(2 * (st.j - 1)) * it.plane;
-    return it.vel + (int64_t)((tau >> 1) & 1) * it.plane;
+    return it.vel + (int64_t)vel_slot(it, tau) * it.plane;
 }
 
 template <typename T, typename Acc>
 __device__ __forceinline__ T* vel_out(const Item<T, Acc>& it, int tau)
 {
-    return it.vel + (int64_t)((tau >> 1) & 1) * it.plane;
+    return it.vel + (int64_t)vel_slot(it, tau) * it.plane;
 }
 
 // Checkpoint pair that level t1 = jK (1 <= j <= J-1, the start of segment j)
@@ -625,17 +687,17 @@ __device__ __forceinline__ void cell_of(int c, int grow, int x0, int z0, int& ix
     iz = z0 - grow + c / W;
 }
 
-// Damping value e = D dt of column x0 - 2 + tid (tid < W0) or of row
-// z0 - 2 + (tid - W0) (W0 <= tid < ND) of the tile grown by two; zero outside
-// the grid.  Loaded with the burst so that the compute phase reads it from LDS.
+// Damping value e = D dt of column x0 - GROW + tid (tid < W0) or of row
+// z0 - GROW + (tid - W0) (W0 <= tid < ND) of the tile grown by GROW cells;
+// zero outside the grid.  Loaded with the burst so that the compute phase reads it from LDS.
 // (nx, nz and the profile pointers come in as values already held in scalar
 // registers: selecting them per lane through the descriptor would turn the
 // selection into a dependent vector load.)
-template <typename T, int W0, int ND>
+template <typename T, int W0, int ND, int GROW = 2>
 __device__ __forceinline__ T damping_of(const T* exd, const T* ezd, int nx, int nz, int tid, int x0, int z0)
 {
     const bool col = tid < W0;
-    const int i = col ? x0 - 2 + tid : z0 - 2 + (tid - W0);
+    const int i = col ? x0 - GROW + tid : z0 - GROW + (tid - W0);
     const bool in = tid < ND && i >= 0 && i < (col ? nx : nz);
     const T v = ldg(col ? exd : ezd, in ? i : 0);
     return in ? v : T(0);
@@ -698,9 +760,9 @@ __device__ void tile_forward2(const Item<T, Acc>& it, const Step& st, int tile_x
         int gx, gz;
         cell_of<T, G, R, false>(c, 2, x0, z0, gx, gz);
         const bool in = c < L::N0 && gx >= 0 && gx < nx && gz >= 0 && gz < nz;
-        const int64_t x = in ? (int64_t)gz * nx + gx : 0;
-        f0[i] = vkeep<T, G>(in, vload<T, G>(cur, x));
-        const T q = ldg(cf, 2 * x), bt = ldg(cf, 2 * x + 1);
+        const uint32_t x = in ? (uint32_t)(gz * nx + gx) : 0u;
+        f0[i] = vkeep<T, G>(in, vload32<T, G>(cur, x));
+        const T q = ldg32(cf, 2 * x), bt = ldg32(cf, 2 * x + 1);
         q0[i] = in ? q : T(0);
         b0[i] = in ? bt : T(0);
     }
@@ -708,13 +770,13 @@ __device__ void tile_forward2(const Item<T, Acc>& it, const Step& st, int tile_x
     for (int k = 0; k < R; ++k) {
         const int iz = z0 + (int)threadIdx.y * R + k;
         const bool in = ix < nx && iz < nz;
-        vt[k] = vkeep<T, G>(in, vload<T, G>(vin, in ? (int64_t)iz * nx + ix : 0));
+        vt[k] = vkeep<T, G>(in, vload32<T, G>(vin, in ? (uint32_t)(iz * nx + ix) : 0u));
     }
     int rex = 0, rez = 0;
     ring_cell<L::W1, L::TZ>(tid, rex, rez);
     const int rix = x0 - 1 + rex, riz = z0 - 1 + rez;
     const bool rin = tid < NR && rix >= 0 && rix < nx && riz >= 0 && riz < nz;
-    vr = vkeep<T, G>(rin, vload<T, G>(vin, rin ? (int64_t)riz * nx + rix : 0));
+    vr = vkeep<T, G>(rin, vload32<T, G>(vin, rin ? (uint32_t)(riz * nx + rix) : 0u));
     const T dmp = damping_of<T, L::W0, L::ND>(exd_p, ezd_p, nx, nz, tid, x0, z0);
 #pragma unroll
     for (int i = 0; i < L::P0; ++i) {
@@ -732,7 +794,7 @@ __device__ void tile_forward2(const Item<T, Acc>& it, const Step& st, int tile_x
     // given there), u^{n+1} returned; the caller knows the cell is in the grid
     auto step1 = [&](int ex, int ez, int gx, int gz, Vec<T, G>& vv) {
         const int k = (ez + 1) * L::W0 + ex + 1;
-        const int64_t x = (int64_t)gz * nx + gx;
+        const uint32_t x = (uint32_t)(gz * nx + gx);
         T fw, fe, fn, fs, nb, c2;
         faces<T>(gx > 0, gx < nx - 1, gz > 0, gz < nz - 1, B0[k], B0[k - 1],
                  B0[k + 1], B0[k - L::W0], B0[k + L::W0], fw, fe, fn, fs);
@@ -761,11 +823,11 @@ __device__ void tile_forward2(const Item<T, Acc>& it, const Step& st, int tile_x
         ut[k] = vzero<T, G>();
         if (ix < nx && iz < nz) {
             ut[k] = step1((int)threadIdx.x + 1, ez + 1, ix, iz, vt[k]);
-            const int64_t x = (int64_t)iz * nx + ix;
-            if (keep1) vstore<T, G>(out1, x, ut[k]);
+            const uint32_t x = (uint32_t)(iz * nx + ix);
+            if (keep1) vstore32<T, G>(out1, x, ut[k]);
             if (ck1) {
-                vstore<T, G>(ck1, x, vt[k]);
-                vstore<T, G>(ck1 + it.plane, x, ut[k]);
+                vstore32<T, G>(ck1, x, vt[k]);
+                vstore32<T, G>(ck1 + it.plane, x, ut[k]);
             }
         }
     }
@@ -783,7 +845,7 @@ __device__ void tile_forward2(const Item<T, Acc>& it, const Step& st, int tile_x
             if (iz < nz) {
                 const int k1 = (ez + 1) * L::W1 + threadIdx.x + 1;
                 const int k0 = (ez + 2) * L::W0 + threadIdx.x + 2;
-                const int64_t x = (int64_t)iz * nx + ix;
+                const uint32_t x = (uint32_t)(iz * nx + ix);
                 T fw, fe, fn, fs, nb, c2;
                 faces<T>(ix > 0, ix < nx - 1, iz > 0, iz < nz - 1, B0[k0], B0[k0 - 1],
                          B0[k0 + 1], B0[k0 - L::W0], B0[k0 + L::W0], fw, fe, fn, fs);
@@ -799,16 +861,237 @@ __device__ void tile_forward2(const Item<T, Acc>& it, const Step& st, int tile_x
                     rv.v[g] = v;
                     r.v[g] = u0.v[g] + v;
                 }
-                vstore<T, G>(out2, x, r);
-                vstore<T, G>(vout, x, rv);
+                vstore32<T, G>(out2, x, r);
+                vstore32<T, G>(vout, x, rv);
                 if (ck2) {
-                    vstore<T, G>(ck2, x, rv);
-                    vstore<T, G>(ck2 + it.plane, x, r);
+                    vstore32<T, G>(ck2, x, rv);
+                    vstore32<T, G>(ck2 + it.plane, x, r);
                 }
             }
         }
     }
     sample_tile2<T, G>(it, rcv, n, U1, L::W1, x0, z0, out2);
+}
+
+// ============================================================== three forward steps per launch
+//
+// The workgroup stages its tile grown by three cells (field, coefficients,
+// damping) in LDS and runs step n on the tile grown by two, step n+1 on the
+// tile grown by one and step n+2 on the tile.  Every level lives in the one
+// LDS plane laid out on the tile grown by three: a step's results are held in
+// registers until every lane has read the level before, then written over
+// it.  A lane keeps v of its cells in registers through the steps that need
+// them: its R tile cells (all three steps), one cell of the ring of the tile
+// grown by one (steps n and n+1) and one of the ring of the tile grown by two
+// (step n).  Only forward-type steps (first pass, recompute) take this form;
+// adjoint launches fuse at most two steps.
+
+template <typename T, int G, int R>
+struct Lds3 {
+    static constexpr int TZ = kWavesZ * R;
+    static constexpr int W3 = kTileX + 6, H3 = TZ + 6, N3 = W3 * H3;   // tile grown by 3
+    static constexpr int P3 = (N3 + kBlock - 1) / kBlock;               // per-thread shares
+    static constexpr int ND = W3 + H3;                                  // damping: columns, then rows
+    static constexpr int NR1 = 2 * (kTileX + 2) + 2 * TZ;               // ring of the tile grown by 1
+    static constexpr int NR2 = 2 * (kTileX + 4) + 2 * (TZ + 2);         // ring of the tile grown by 2
+    static_assert(ND <= kBlock && NR1 <= kBlock && NR2 <= kBlock, "one ring cell and damping value per thread");
+    // F[N3] fields, Q[N3] and B[N3] coefficients, D[ND] damping values
+    static constexpr size_t bytes = ((size_t)N3 * (G + 2) + (size_t)ND) * sizeof(T);
+    // workgroups of 4 waves that the 160 KiB of LDS of a CU hold = waves per
+    // SIMD (at most 6); the register allocation is held to what that
+    // occupancy allows, so registers do not lower it further
+    static constexpr int kWaves = (int)(160 * 1024 / bytes) < 6 ? (int)(160 * 1024 / bytes) : 6;
+};
+
+// Traces d[m] from an LDS level laid out on the tile grown by GROW (row
+// width W), at the receivers of one tile.  The caller has made the level
+// visible to the workgroup and does not overwrite it before a barrier.
+template <typename T, int G, int GROW, typename Acc>
+__device__ __forceinline__ void sample_lds(const Item<T, Acc>& it, Span sp, int m, const Vec<T, G>* U, int W,
+                                           int x0, int z0)
+{
+    const int tid = threadIdx.y * kTileX + threadIdx.x;
+    for (int e = sp.e0 + tid; e < sp.e1; e += kBlock) {
+        const Entry en = ld_entry(it.entries, e);
+        const int cell = en.slot / G, g = en.slot - cell * G;
+        const int k = (cell / it.nx - z0 + GROW) * W + (cell % it.nx - x0 + GROW);
+        stg(it.traces, en.trace_off + (int64_t)m * it.n_rcv, U[k].v[g]);
+    }
+}
+
+template <typename T, int G, typename Acc, int R, int V = 0>
+__device__ void tile_forward3(const Item<T, Acc>& it, const Step& st, int tile_x, int tile_z, bool sample,
+                              unsigned char* smem)
+{
+    using L = Lds3<T, G, R>;
+    constexpr int W = L::W3;
+    const int nx = it.nx, nz = it.nz, n = st.n;
+    Vec<T, G>* U = reinterpret_cast<Vec<T, G>*>(smem);                   // u^n, then u^{n+1}, u^{n+2}
+    T* Q = reinterpret_cast<T*>(U + L::N3);                              // q, tile + 3
+    T* B = Q + L::N3;                                                    // bt, tile + 3
+    T* D = B + L::N3;                                                    // damping
+    const T* cur = fwd_plane(it, st, n);
+    const T* vin = vel_in(it, st, n);
+    T* out1 = it.seg + (int64_t)(n % it.K) * it.plane;
+    T* out2 = it.seg + (int64_t)((n + 1) % it.K) * it.plane;
+    T* out3 = it.seg + (int64_t)((n + 2) % it.K) * it.plane;
+    T* vout = vel_out(it, n + 3);
+    T* ck1 = ckpt_pair(it, st, n + 1);
+    T* ck2 = ckpt_pair(it, st, n + 2);
+    T* ck3 = ckpt_pair(it, st, n + 3);
+    // u^{n+1} and u^{n+2} are stored only where the adjoint will read them
+    const bool keep1 = st.phase != kFwd || n + 1 >= it.keep_from;
+    const bool keep2 = st.phase != kFwd || n + 2 >= it.keep_from;
+    const Src<T, G> s1 = sources<T, G>(it, n);
+    const Src<T, G> s2 = sources<T, G>(it, n + 1);
+    const Src<T, G> s3 = sources<T, G>(it, n + 2);
+    const Span rcv = sample ? span_of(it.tile_off, tile_z * it.tiles_x + tile_x) : Span{0, 0};
+    const int x0 = tile_x * kTileX, z0 = tile_z * L::TZ;
+    const int tid = threadIdx.y * kTileX + threadIdx.x;
+    const int tx = (int)threadIdx.x, ix = x0 + tx;
+    const T* cf = it.coef;
+
+    // this lane's ring cells, relative to the tile origin
+    int r1x = 0, r1z = 0, r2x = 0, r2z = 0;
+    ring_cell<kTileX + 2, L::TZ>(tid, r1x, r1z);
+    ring_cell<kTileX + 4, L::TZ + 2>(tid, r2x, r2z);
+    r1x -= 1; r1z -= 1; r2x -= 2; r2z -= 2;
+    const bool in1 = tid < L::NR1 && x0 + r1x >= 0 && x0 + r1x < nx && z0 + r1z >= 0 && z0 + r1z < nz;
+    const bool in2 = tid < L::NR2 && x0 + r2x >= 0 && x0 + r2x < nx && z0 + r2z >= 0 && z0 + r2z < nz;
+
+    // one burst: u^n and (q, bt) on the tile grown by 3; v^n at this lane's
+    // cells; the damping profile
+    Vec<T, G> f[L::P3], vt[R], v1, v2;
+    T q[L::P3], b[L::P3];
+#pragma unroll
+    for (int i = 0; i < L::P3; ++i) {
+        const int c = tid + i * kBlock;
+        int gx, gz;
+        cell_of<T, G, R, false>(c, 3, x0, z0, gx, gz);
+        const bool in = c < L::N3 && gx >= 0 && gx < nx && gz >= 0 && gz < nz;
+        const uint32_t x = in ? (uint32_t)(gz * nx + gx) : 0u;
+        f[i] = vkeep<T, G>(in, vload32<T, G>(cur, x));
+        const T qv = ldg32(cf, 2 * x), bv = ldg32(cf, 2 * x + 1);
+        q[i] = in ? qv : T(0);
+        b[i] = in ? bv : T(0);
+    }
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        const int iz = z0 + (int)threadIdx.y * R + k;
+        const bool in = ix < nx && iz < nz;
+        vt[k] = vkeep<T, G>(in, vload32<T, G>(vin, in ? (uint32_t)(iz * nx + ix) : 0u));
+    }
+    v1 = vkeep<T, G>(in1, vload32<T, G>(vin, in1 ? (uint32_t)((z0 + r1z) * nx + x0 + r1x) : 0u));
+    v2 = vkeep<T, G>(in2, vload32<T, G>(vin, in2 ? (uint32_t)((z0 + r2z) * nx + x0 + r2x) : 0u));
+    const T dmp = damping_of<T, W, L::ND, 3>(it.ex, it.ez, nx, nz, tid, x0, z0);
+#pragma unroll
+    for (int i = 0; i < L::P3; ++i) {
+        const int c = tid + i * kBlock;
+        if (c < L::N3) {
+            U[c] = f[i];
+            Q[c] = q[i];
+            B[c] = b[i];
+        }
+    }
+    if (tid < L::ND) D[tid] = dmp;
+    __syncthreads();
+
+    // one step at cell (x, z) of the grid (tile-relative) from the level in
+    // U: v of the next level into vv (v of this level given there), u of the
+    // next level returned
+    auto step = [&](int x, int z, Vec<T, G>& vv, const Src<T, G>& sc) {
+        const int gx = x0 + x, gz = z0 + z;
+        const int k = (z + 3) * W + x + 3;
+        const int cell = gz * nx + gx;
+        T fw, fe, fn, fs, nb, c2;
+        faces<T>(gx > 0, gx < nx - 1, gz > 0, gz < nz - 1, B[k], B[k - 1], B[k + 1], B[k - W], B[k + W],
+                 fw, fe, fn, fs);
+        damp_inc<T>(D[x + 3] + D[W + z + 3], nb, c2);
+        const T qc = Q[k];
+        const Vec<T, G> u0 = U[k], uw = U[k - 1], ue = U[k + 1], un = U[k - W], us = U[k + W];
+        Vec<T, G> r;
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            T v = fwd_cell<T>(nb, c2, qc, fw, fe, fn, fs, u0.v[g], uw.v[g], ue.v[g], un.v[g], us.v[g], vv.v[g]);
+            if (cell == sc.cell[g]) v += sc.w[g];
+            vv.v[g] = v;
+            r.v[g] = u0.v[g] + v;
+        }
+        return r;
+    };
+    auto lds_at = [&](int x, int z) { return (z + 3) * W + x + 3; };
+
+    // step n on the tile grown by two
+    Vec<T, G> a1 = vzero<T, G>(), a2 = vzero<T, G>(), at[R];
+    if (in2) a2 = step(r2x, r2z, v2, s1);
+    if (in1) a1 = step(r1x, r1z, v1, s1);
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        const int z = (int)threadIdx.y * R + k, iz = z0 + z;
+        at[k] = vzero<T, G>();
+        if (ix < nx && iz < nz) {
+            at[k] = step(tx, z, vt[k], s1);
+            const uint32_t x = (uint32_t)(iz * nx + ix);
+            if (keep1) vstore32<T, G>(out1, x, at[k]);
+            if (ck1) {
+                vstore32<T, G>(ck1, x, vt[k]);
+                vstore32<T, G>(ck1 + it.plane, x, at[k]);
+            }
+        }
+    }
+    __syncthreads();
+    if (tid < L::NR2) U[lds_at(r2x, r2z)] = a2;
+    if (tid < L::NR1) U[lds_at(r1x, r1z)] = a1;
+#pragma unroll
+    for (int k = 0; k < R; ++k) U[lds_at(tx, (int)threadIdx.y * R + k)] = at[k];
+    __syncthreads();
+    if (rcv.e1 > rcv.e0) sample_lds<T, G, 3>(it, rcv, n, U, W, x0, z0);
+
+    // step n+1 on the tile grown by one
+    if (in1) a1 = step(r1x, r1z, v1, s2);
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        const int z = (int)threadIdx.y * R + k, iz = z0 + z;
+        if (ix < nx && iz < nz) {
+            at[k] = step(tx, z, vt[k], s2);
+            const uint32_t x = (uint32_t)(iz * nx + ix);
+            if (keep2) vstore32<T, G>(out2, x, at[k]);
+            if (ck2) {
+                vstore32<T, G>(ck2, x, vt[k]);
+                vstore32<T, G>(ck2 + it.plane, x, at[k]);
+            }
+        }
+    }
+    __syncthreads();
+    if (tid < L::NR1) U[lds_at(r1x, r1z)] = a1;
+#pragma unroll
+    for (int k = 0; k < R; ++k) U[lds_at(tx, (int)threadIdx.y * R + k)] = at[k];
+    __syncthreads();
+    if (rcv.e1 > rcv.e0) sample_lds<T, G, 3>(it, rcv, n + 1, U, W, x0, z0);
+
+    // step n+2 on the tile
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        const int z = (int)threadIdx.y * R + k, iz = z0 + z;
+        if (ix < nx && iz < nz) {
+            const Vec<T, G> r = step(tx, z, vt[k], s3);
+            const uint32_t x = (uint32_t)(iz * nx + ix);
+            vstore32<T, G>(out3, x, r);
+            vstore32<T, G>(vout, x, vt[k]);
+            if (ck3) {
+                vstore32<T, G>(ck3, x, vt[k]);
+                vstore32<T, G>(ck3 + it.plane, x, r);
+            }
+        }
+    }
+    // trace d[n+2] from the stored u^{n+3}
+    if (rcv.e1 > rcv.e0) {
+        __syncthreads();
+        for (int e = rcv.e0 + tid; e < rcv.e1; e += kBlock) {
+            const Entry en = ld_entry(it.entries, e);
+            stg(it.traces, en.trace_off + (int64_t)(n + 2) * it.n_rcv, ldg(out3, en.slot));
+        }
+    }
 }
 
 template <typename T, int G, typename Acc, int R, int V = 0>
@@ -854,9 +1137,9 @@ __device__ void tile_adjoint2(const Item<T, Acc>& it, const Step& st, int tile_x
         int ix0, iz0;
         cell_of<T, G, R, true>(c, 2, x0, z0, ix0, iz0);
         const bool in = c < L::N0 && ix0 >= 0 && ix0 < nx && iz0 >= 0 && iz0 < nz;
-        const int64_t x = in ? (int64_t)iz0 * nx + ix0 : 0;
-        f0[i] = vkeep<T, G>(in, vload<T, G>(cur, x));
-        const T q = ldg(cf, 2 * x), bt = ldg(cf, 2 * x + 1);
+        const uint32_t x = in ? (uint32_t)(iz0 * nx + ix0) : 0u;
+        f0[i] = vkeep<T, G>(in, vload32<T, G>(cur, x));
+        const T q = ldg32(cf, 2 * x), bt = ldg32(cf, 2 * x + 1);
         q0[i] = in ? q : T(0);
         b0[i] = in ? bt : T(0);
     }
@@ -866,17 +1149,17 @@ __device__ void tile_adjoint2(const Item<T, Acc>& it, const Step& st, int tile_x
         int ix1, iz1;
         cell_of<T, G, R, true>(c, 1, x0, z0, ix1, iz1);
         const bool in = c < L::N1 && ix1 >= 0 && ix1 < nx && iz1 >= 0 && iz1 < nz;
-        const int64_t x = in ? (int64_t)iz1 * nx + ix1 : 0;
-        pv[i] = vkeep<T, G>(in, vload<T, G>(p1, x));
-        ua[i] = vkeep<T, G>(in, vload<T, G>(um1, x));
-        ub[i] = vkeep<T, G>(in, vload<T, G>(um2, x));
+        const uint32_t x = in ? (uint32_t)(iz1 * nx + ix1) : 0u;
+        pv[i] = vkeep<T, G>(in, vload32<T, G>(p1, x));
+        ua[i] = vkeep<T, G>(in, vload32<T, G>(um1, x));
+        ub[i] = vkeep<T, G>(in, vload32<T, G>(um2, x));
     }
 #pragma unroll
     for (int k = 0; k < R; ++k) {
         const int iz = z0 + (int)threadIdx.y * R + k;
-        const int64_t x = ix < nx && iz < nz ? (int64_t)iz * nx + ix : 0;
-        sK[k] = ldg(accK, x);
-        sB[k] = ldg(accB, x);
+        const uint32_t x = ix < nx && iz < nz ? (uint32_t)(iz * nx + ix) : 0u;
+        sK[k] = ldg32(accK, x);
+        sB[k] = ldg32(accB, x);
     }
     const T dmp = damping_of<T, L::W0, L::ND>(exd_p, ezd_p, nx, nz, tid, x0, z0);
 #pragma unroll
@@ -985,7 +1268,7 @@ __device__ void tile_adjoint2(const Item<T, Acc>& it, const Step& st, int tile_x
             if (iz < nz) {
                 const int k1 = (ez + 1) * L::W1 + threadIdx.x + 1;
                 const int k0 = (ez + 2) * L::W0 + threadIdx.x + 2;
-                const int64_t x = (int64_t)iz * nx + ix;
+                const uint32_t x = (uint32_t)(iz * nx + ix);
                 const bool hn = iz > 0, hs = iz < nz - 1;
                 T fw, fe, fn, fs, a, b;
                 faces<T>(hw, he, hn, hs, B0[k0], B0[k0 - 1], B0[k0 + 1],
@@ -1012,8 +1295,8 @@ __device__ void tile_adjoint2(const Item<T, Acc>& it, const Step& st, int tile_x
                     skb += Acc(k1b);
                     sbb += Acc(b1b);
                 }
-                vstore<T, G>(out1, x, m0);
-                vstore<T, G>(out2, x, r);
+                vstore32<T, G>(out1, x, m0);
+                vstore32<T, G>(out2, x, r);
                 // the two time levels' imaging sums are added to the accumulators one
                 // after the other, exactly as two one-step launches would
                 Acc vk = sK[k], vb = sB[k];
@@ -1021,8 +1304,8 @@ __device__ void tile_adjoint2(const Item<T, Acc>& it, const Step& st, int tile_x
                 vb += sba[k];
                 vk += skb;
                 vb += sbb;
-                stg(accK, x, vk);
-                stg(accB, x, vb);
+                stg32(accK, x, vk);
+                stg32(accB, x, vb);
             }
         }
     }
@@ -1036,7 +1319,7 @@ __device__ __forceinline__ Step item_step(const Item<T, Acc>& it, int s, int mod
 {
     int sl = s;
     if (mode == kRunAdjOnly) sl = s + (it.nt + it.S - 1) / it.S;
-    Step st = decode(it.nt, it.K, it.J, sl, it.S);
+    Step st = decode(it.nt, it.K, it.J, sl, it.S, it.Sa);
     if (mode == kRunFwdOnly && st.phase != kFwd) st.phase = kIdle;
     return st;
 }
@@ -1066,6 +1349,20 @@ __global__ __launch_bounds__(kBlock) void fwd2_kernel(const Item<T, Acc>* __rest
     const Step st = item_step(it, s, mode);
     if ((st.phase != kFwd && st.phase != kRecomp) || st.count != 2) return;
     tile_forward2<T, G, Acc, R>(it, st, bt.y % it.tiles_x, bt.y / it.tiles_x, st.phase == kFwd && it.sample, smem);
+}
+
+// Forward-type launches of three steps, tiles of 64 x 4R cells.
+template <typename T, int G, typename Acc, int R>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(Lds3<T, G, R>::kWaves))) void fwd3_kernel(const Item<T, Acc>* __restrict__ items,
+                                                       const int2* __restrict__ blocks, int s, int mode)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int2 bt = blocks[blockIdx.x];
+    if (bt.x < 0) return;
+    const Item<T, Acc>& it = items[bt.x];
+    const Step st = item_step(it, s, mode);
+    if ((st.phase != kFwd && st.phase != kRecomp) || st.count != 3) return;
+    tile_forward3<T, G, Acc, R>(it, st, bt.y % it.tiles_x, bt.y / it.tiles_x, st.phase == kFwd && it.sample, smem);
 }
 
 // Adjoint + imaging launches of one step.

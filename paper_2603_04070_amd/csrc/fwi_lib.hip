@@ -66,6 +66,7 @@ struct fwi_plan {
     fwi_dtype dtype = FWI_F32;
     fwi_options opt{};
     int G = 1, rows = 4, S = 1, nlam = 2, order = 2;
+    int Sa = 1;                     // adjoint steps per launch (S: forward-type steps)
     bool acc_double = false;
     size_t tsize = 4, asize = 4;
     std::vector<MediumPlan> media;
@@ -181,16 +182,20 @@ fwi_status validate_grid(const fwi_grid& g, int idx, std::string& msg, int order
 }
 
 // Step launches per (dtype, accumulator, G).  kind: 0 forward one step,
-// 1 forward two steps, 2 adjoint one step, 3 adjoint two steps.  Two-step
-// kernels exist for tile heights of 4, 8 and 16 rows (R = 1, 2, 4).
+// 1 forward two steps, 2 adjoint one step, 3 adjoint two steps, 4 forward
+// three steps.  Multi-step kernels exist for tile heights of 4, 8 and 16 rows
+// (R = 1, 2, 4).
 template <typename T, typename Acc, int G, int R>
 void launch2(int kind, dim3 grid, hipStream_t st, const Item<T, Acc>* it, const int2* blocks, int s, int mode)
 {
     const dim3 blk(kTileX, kWavesZ);
     constexpr size_t lds_f = Lds2<T, G, R, false>::bytes;
     constexpr size_t lds_a = Lds2<T, G, R, true>::bytes;
+    constexpr size_t lds_3 = Lds3<T, G, R>::bytes;
     if (kind == 1)
         hipLaunchKernelGGL((fwd2_kernel<T, G, Acc, R>), grid, blk, lds_f, st, it, blocks, s, mode);
+    else if (kind == 4)
+        hipLaunchKernelGGL((fwd3_kernel<T, G, Acc, R>), grid, blk, lds_3, st, it, blocks, s, mode);
     else
         hipLaunchKernelGGL((adj2_kernel<T, G, Acc, R>), grid, blk, lds_a, st, it, blocks, s, mode);
 }
@@ -240,6 +245,9 @@ hipError_t allow_lds()
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&fwd2_kernel<T, G, Acc, R>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)Lds2<T, G, R, false>::bytes);
     if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&fwd3_kernel<T, G, Acc, R>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)Lds3<T, G, R>::bytes);
+    if (e != hipSuccess) return e;
     return hipFuncSetAttribute(reinterpret_cast<const void*>(&adj2_kernel<T, G, Acc, R>),
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)Lds2<T, G, R, true>::bytes);
 }
@@ -288,7 +296,7 @@ void step(fwi_plan* p, int kind, dim3 grid, hipStream_t st, const int2* blocks, 
 
 hipError_t allow_lds_plan(const fwi_plan* p)
 {
-    if (p->S != 2 && p->order != 4) return hipSuccess;
+    if (p->S < 2 && p->order != 4) return hipSuccess;
     auto pick = [&](auto t, auto a) -> hipError_t {
         using T = decltype(t);
         using A = decltype(a);
@@ -373,39 +381,20 @@ void launch_persistent(fwi_plan* p, hipStream_t st, const Wave& w, int mode_idx,
 }
 
 // Launch kinds present in a wave at launch s of a call: bit k set when some
-// item needs kind k (host mirror of the device schedule).
+// item needs kind k (the schedule the kernels decode, evaluated on the host).
 unsigned wave_kinds(const fwi_plan* p, const Wave& w, int s, int mode, int* n_active)
 {
-    const int S = p->S;
     unsigned bits = 0;
     *n_active = 0;
     for (int pos = 0; pos < (int)w.items.size(); ++pos) {
         const ItemPlan& it = p->items[w.items[pos]];
-        const unsigned before = bits;
-        const int T = p->media[it.medium].g.nt, K = it.K, J = it.J;
-        const int nf = (T + S - 1) / S;
-        int sl = mode == kRunAdjOnly ? s + nf : s;
-        bool active = false;
-        if (sl < nf) {
-            bits |= std::min(S, T - sl * S) == 2 ? 2u : 1u;
-            active = true;
-        } else if (mode != kRunFwdOnly) {
-            sl -= nf;
-            const int last = T - (J - 1) * K, nl = (last + S - 1) / S;
-            const int nk = (K + S - 1) / S;
-            if (sl < nl) {
-                bits |= std::min(S, last - sl * S) == 2 ? 8u : 4u;
-                active = true;
-            } else if (sl - nl < 2 * nk * (J - 1)) {
-                const int rem = (sl - nl) % (2 * nk);
-                const int m = rem < nk ? rem : rem - nk;
-                const bool two = std::min(S, K - m * S) == 2;
-                bits |= rem < nk ? (two ? 2u : 1u) : (two ? 8u : 4u);
-                active = true;
-            }
-        }
-        (void)before;
-        if (active) *n_active = pos + 1;
+        const int T = p->media[it.medium].g.nt;
+        const int nf = (T + p->S - 1) / p->S;
+        const Step st = decode(T, it.K, it.J, mode == kRunAdjOnly ? s + nf : s, p->S, p->Sa);
+        if (st.phase == kIdle || (mode == kRunFwdOnly && st.phase != kFwd)) continue;
+        if (st.phase == kAdj) bits |= st.count == 2 ? 8u : 4u;
+        else bits |= st.count == 3 ? 16u : st.count == 2 ? 2u : 1u;
+        *n_active = pos + 1;
     }
     return bits;
 }
@@ -464,7 +453,10 @@ static fwi_status create_impl(fwi_plan* p, fwi_dtype dtype, const fwi_grid* grid
         return fail(p, FWI_ERR_INVALID, "group must be 0, 1, 2 or 4");
     if (o.mode == FWI_PLAIN && o.group > 1) return fail(p, FWI_ERR_INVALID, "plain mode runs one transmit per item");
     if (o.rows < 0 || o.rows > 64) return fail(p, FWI_ERR_INVALID, "rows must be in [0, 64]");
-    if (o.steps_per_launch < 0 || o.steps_per_launch > 2) return fail(p, FWI_ERR_INVALID, "steps_per_launch must be 0, 1 or 2");
+    if (o.steps_per_launch < 0 || o.steps_per_launch > 3)
+        return fail(p, FWI_ERR_INVALID, "steps_per_launch must be 0, 1, 2 or 3");
+    if (o.persistent && o.steps_per_launch == 3)
+        return fail(p, FWI_ERR_INVALID, "the persistent form fuses at most two steps per launch");
     if (o.ckpt_interval < 0) return fail(p, FWI_ERR_INVALID, "ckpt_interval must be >= 0");
     if (o.mem_budget < 0) return fail(p, FWI_ERR_INVALID, "mem_budget must be >= 0");
     if (o.use_graph && o.mode != FWI_BATCHED) return fail(p, FWI_ERR_INVALID, "use_graph requires FWI_BATCHED");
@@ -475,7 +467,7 @@ static fwi_status create_impl(fwi_plan* p, fwi_dtype dtype, const fwi_grid* grid
     if (o.order != 0 && o.order != 2 && o.order != 4) return fail(p, FWI_ERR_INVALID, "order must be 0, 2 or 4");
     if (o.order == 4) {
         if (o.persistent) return fail(p, FWI_ERR_INVALID, "the fourth-order operator has no persistent form");
-        if (o.steps_per_launch == 2) return fail(p, FWI_ERR_INVALID, "the fourth-order operator runs one step per launch");
+        if (o.steps_per_launch >= 2) return fail(p, FWI_ERR_INVALID, "the fourth-order operator runs one step per launch");
         if (o.rows != 0 && o.rows != 1 && o.rows != 2 && o.rows != 4)
             return fail(p, FWI_ERR_INVALID, "the fourth-order operator needs rows of 1, 2 or 4");
     }
@@ -488,8 +480,9 @@ static fwi_status create_impl(fwi_plan* p, fwi_dtype dtype, const fwi_grid* grid
     p->dtype = dtype;
     p->opt = o;
     p->G = o.group ? o.group : (o.mode == FWI_PLAIN ? 1 : 4);
-    // default: two steps per launch on 64 x 8 tiles (one step on 64 x 16 for the plain
-    // form); with an explicit rows value that two-step tiles do not support, one step
+    // default: three forward-type and two adjoint steps per launch on 64 x 8
+    // tiles (one step on 64 x 16 for the plain form); with an explicit rows
+    // value that multi-step tiles do not support, one step
     auto two_step_ok = [&](int rows) {
         if (rows != 1 && rows != 2 && rows != 4) return false;
         // LDS of the two-step adjoint: tile + 2 (fields, q, bt) and two tile + 1
@@ -506,6 +499,12 @@ static fwi_status create_impl(fwi_plan* p, fwi_dtype dtype, const fwi_grid* grid
         const size_t n4 = (size_t)(kTileX + 6) * (kWavesZ * p->rows + 6);
         if (n4 * (2 * p->G + 2) * ts > kLdsBytes)
             return fail(p, FWI_ERR_INVALID, "the fourth-order tile of these rows does not fit the LDS");
+    } else if (o.steps_per_launch == 3) {
+        // three forward-type steps and two adjoint steps per launch
+        p->S = 3;
+        p->rows = o.rows ? o.rows : 2;
+        if (!two_step_ok(p->rows))
+            return fail(p, FWI_ERR_INVALID, "multi-step launches need rows of 1, 2 or 4 whose tile fits the LDS");
     } else if (o.steps_per_launch == 2) {
         p->S = 2;
         p->rows = o.rows ? o.rows : 2;
@@ -515,8 +514,10 @@ static fwi_status create_impl(fwi_plan* p, fwi_dtype dtype, const fwi_grid* grid
         p->S = 1;
         p->rows = o.rows ? o.rows : 4;
     } else {
+        // default: three forward steps and two adjoint steps per launch (two
+        // and two for the persistent form)
         p->rows = o.rows ? o.rows : 2;
-        p->S = two_step_ok(p->rows) ? 2 : 1;
+        p->S = two_step_ok(p->rows) ? (o.persistent ? 2 : 3) : 1;
     }
     p->acc_double = dtype == FWI_F64 || o.acc_double;
     p->tsize = dtype == FWI_F64 ? 8 : 4;
@@ -533,6 +534,11 @@ static fwi_status create_impl(fwi_plan* p, fwi_dtype dtype, const fwi_grid* grid
         m.rcv.assign(grids[i].rcv, grids[i].rcv + (size_t)grids[i].n_tx * grids[i].n_rcv);
         m.g.src = nullptr;
         m.g.rcv = nullptr;
+        // the step kernels address a field plane ([nz][nx][G]) and the
+        // coefficient array ([nz][nx][2]) with 32-bit byte offsets
+        const uint64_t span = (uint64_t)m.g.nx * m.g.nz * (uint64_t)std::max(G, 2) * p->tsize;
+        if (span >= (1ULL << 32))
+            return fail(p, FWI_ERR_INVALID, "grid too large: nx*nz*max(group,2)*sizeof(dtype) must be below 4 GiB");
         m.dmax = dmax_of(m.g);
         m.item0 = (int)p->items.size();
         for (int tx = 0; tx < m.g.n_tx; tx += G) {
@@ -570,8 +576,10 @@ static fwi_status create_impl(fwi_plan* p, fwi_dtype dtype, const fwi_grid* grid
     auto auto_k = [&](int T) {
         if (T <= 2) return T;
         int K = (int)std::lround(std::sqrt(2.0 * T));
-        // an even K lets two-step launches tile every segment exactly
+        // an even K lets two-step launches tile every segment exactly; with
+        // three forward steps per launch K is a multiple of 6
         if (p->S == 2 && K % 2) ++K;
+        if (p->S == 3 && K % 6) K += 6 - K % 6;
         return std::max(2, std::min(K, T));
     };
     for (auto& it : p->items) {
@@ -653,17 +661,25 @@ static fwi_status create_impl(fwi_plan* p, fwi_dtype dtype, const fwi_grid* grid
             if (!w.items.empty()) p->waves.push_back(w);
         }
     }
-    // two steps per launch read and write four field planes of the segment
-    // buffer at once: that needs K >= 4 wherever the buffer wraps
-    if (p->S == 2)
+    // three forward steps per launch: recompute runs must start at multiples
+    // of 3 (the v slot rule), so K is a multiple of 3 wherever there is replay
+    if (p->S == 3)
+        for (auto& it : p->items) {
+            const int T = p->media[it.medium].g.nt;
+            if (it.K < T && !o.forward_only && it.K % 3) p->S = 2;
+        }
+    // a launch of two or three steps reads and writes up to four field planes
+    // of the segment buffer at once: that needs K >= 4 wherever the buffer wraps
+    if (p->S >= 2)
         for (auto& it : p->items)
             if (it.K < 4 && it.K < p->media[it.medium].g.nt) p->S = 1;
-    p->nlam = p->S == 2 ? 4 : 2;
+    p->Sa = std::min(p->S, 2);
+    p->nlam = p->Sa == 2 ? 4 : 2;
     for (auto& it : p->items) {
         const int T = p->media[it.medium].g.nt;
         it.J = o.forward_only ? 1 : (T + it.K - 1) / it.K;
-        const int S = p->S, last = T - (it.J - 1) * it.K;
-        it.steps = (T + S - 1) / S + (last + S - 1) / S + 2 * ((it.K + S - 1) / S) * (it.J - 1);
+        const int S = p->S, Sa = p->Sa, last = T - (it.J - 1) * it.K;
+        it.steps = (T + S - 1) / S + (last + Sa - 1) / Sa + ((it.K + S - 1) / S + (it.K + Sa - 1) / Sa) * (it.J - 1);
         const MediumPlan& m = p->media[it.medium];
         p->recompute_updates += (int64_t)it.K * (it.J - 1) * m.g.nx * m.g.nz * it.g_used;
     }
@@ -982,6 +998,7 @@ void fill_descriptors(fwi_plan* p, const fwi_io* io, unsigned char* ws, bool adj
         d.tile_off_x = reinterpret_cast<const int32_t*>(tabs + ip.tile_off_x_off);
         d.entries_x = reinterpret_cast<const Entry*>(tabs + ip.entry_x_off);
         d.S = p->S;
+        d.Sa = p->Sa;
         d.nlam = p->nlam;
         // the adjoint of the last segment reads levels (J-1)K + 1 .. T of the first pass
         d.keep_from = p->opt.forward_only ? INT_MAX : (ip.J - 1) * ip.K + 1;
@@ -1062,7 +1079,7 @@ void enqueue_sequence(fwi_plan* p, hipStream_t st, unsigned char* ws, int call, 
             int n_active = 0;
             const unsigned kinds = wave_kinds(p, w, s, mode, &n_active);
             const dim3 grid((unsigned)w.prefix[n_active]);
-            for (int k = 0; k < 4; ++k)
+            for (int k = 0; k < 5; ++k)
                 if (kinds & (1u << k)) step(p, k, grid, st, p->d_blocks + w.blk0, s, mode);
         }
     }
@@ -1349,7 +1366,7 @@ extern "C" fwi_status fwi_autotune(fwi_dtype dtype, const fwi_grid* grids, int32
     }
     TuneChoice best;
     if (ok) {
-        const int cands[][2] = {{2, 1}, {2, 2}, {2, 4}, {1, 2}, {1, 4}, {1, 8}};
+        const int cands[][2] = {{3, 1}, {3, 2}, {3, 4}, {2, 1}, {2, 2}, {2, 4}, {1, 2}, {1, 4}, {1, 8}};
         hipEvent_t e0, e1;
         (void)hipEventCreate(&e0);
         (void)hipEventCreate(&e1);
@@ -1358,7 +1375,7 @@ extern "C" fwi_status fwi_autotune(fwi_dtype dtype, const fwi_grid* grids, int32
         for (int gi = 0; gi < n_groups; ++gi)
         for (auto& cd : cands) {
             const int grp = G ? G : groups_auto[gi];
-            if (o.mode == FWI_PLAIN && cd[0] == 2) continue;
+            if (o.mode == FWI_PLAIN && cd[0] >= 2) continue;
             fwi_options po = o;
             po.group = grp;
             po.steps_per_launch = cd[0];

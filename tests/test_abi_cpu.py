@@ -102,7 +102,9 @@ def _grid(**kw):
     ({}, dict(rows=100), 1),
     ({}, dict(mode="plain", use_graph=True), 1),
     ({}, dict(steps_per_launch=2, rows=3), 1),
-    ({}, dict(steps_per_launch=3), 1),
+    ({}, dict(steps_per_launch=4), 1),
+    ({}, dict(steps_per_launch=3, persistent=True), 1),
+    ({}, dict(order=4, steps_per_launch=3), 1),
     ({}, dict(order=3), 1),
     (dict(c_max=3100.0), dict(order=4), 2),                 # c dt/h = 0.62 > 0.606 (order 4 only)
     ({}, dict(order=4, persistent=True), 1),

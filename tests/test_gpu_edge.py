@@ -25,7 +25,7 @@ def _close(res, ref, tol=1e-10):
 
 
 @pytest.mark.parametrize("nt", [1, 2, 3])
-@pytest.mark.parametrize("spl,ckpt", [(1, 0), (2, 0), (1, 2), (2, 10**6)])
+@pytest.mark.parametrize("spl,ckpt", [(1, 0), (2, 0), (1, 2), (2, 10**6), (3, 0), (3, 10**6)])
 def test_smallest_grid_few_steps(nt, spl, ckpt):
     """7 x 7 cells (2 npml + 3 with npml = 2): one tile, most of it outside
     the grid; sources and receivers on the border; 1-3 steps."""
@@ -43,7 +43,7 @@ def test_no_absorbing_layer():
     m = W.small_random_medium(42, 90, 70, 140, n_tx=3, n_rcv=5, npml=0, courant=0.5)
     obs = _obs(m, 2)
     ref = oracle_grad(m, obs)
-    for spl in (1, 2):
+    for spl in (1, 2, 3):
         res, _ = gpu_run([m], [obs], dtype="f64", steps_per_launch=spl, ckpt=9)
         _close(res[0], ref)
 

@@ -28,9 +28,9 @@ def test_uneven64_full_size_sampled():
     grids = [F.GridSpec.of(m.geom, c_max) for m in media]
     torch.cuda.empty_cache()
     free, _ = torch.cuda.mem_get_info()
-    plan = F.Plan(grids, dtype="f32", steps_per_launch=2, rows=2, group=4, mem_budget=0.85 * free)
+    plan = F.Plan(grids, dtype="f32", steps_per_launch=3, rows=2, group=4, mem_budget=0.85 * free)
     info = plan.info
-    assert info["steps_per_launch"] == 2 and info["recompute_updates"] > 0
+    assert info["steps_per_launch"] == 3 and info["recompute_updates"] > 0
     dev = torch.device("cuda:0")
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float32)).to(dev)
     ios = []

@@ -209,7 +209,52 @@ def test_two_step_uneven_and_split():
         assert rel_l2(r["grad_rho"], ref["grad_rho"]) <= 1e-10
 
 
-@pytest.mark.parametrize("spl", [1, 2])
+# ---------------------------------------------------------------- three forward steps per launch
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("ckpt,rows,nt", [(0, 2, 100), (9, 2, 101), (10**6, 1, 101), (6, 1, 100), (12, 4, 99)])
+def test_three_step_launches(dtype, ckpt, rows, nt):
+    """Three forward-type steps per launch (two adjoint steps): parity with
+    the oracle on a medium whose sources and receivers sit on tile seams,
+    with first-pass tails of one and two steps."""
+    m = _seam_medium(41, nt=nt)
+    obs = _observed(m, 7)
+    ref = oracle_grad(m, obs)
+    res, plan = gpu_run([m], [obs], dtype=dtype, ckpt=ckpt, rows=rows, steps_per_launch=3)
+    assert plan.info["steps_per_launch"] == 3
+    _check(res[0], ref, dtype)
+
+
+def test_three_step_bitwise_two_step_and_store_all():
+    """Grouping the forward steps three to a launch changes no cell's
+    arithmetic: traces, misfit and gradients equal the two-step plan's
+    bitwise, and checkpointed replay (K = 6, 9, automatic) equals store-all."""
+    m = W.small_random_medium(42, 97, 70, 121, n_tx=4, n_rcv=6, npml=3)
+    obs = _observed(m, 8)
+    ref, _ = gpu_run([m], [obs], dtype="f32", ckpt=10**6, steps_per_launch=2)
+    for K in (10**6, 9, 6, 0):
+        res, plan = gpu_run([m], [obs], dtype="f32", ckpt=K, steps_per_launch=3)
+        assert plan.info["steps_per_launch"] == 3
+        for k in ("traces", "grad_c", "grad_rho", "misfit"):
+            assert np.array_equal(res[0][k], ref[0][k]), (K, k)
+
+
+def test_three_step_uneven_media_and_fallback():
+    """Uneven media in one three-step plan pass parity; an interval that is
+    not a multiple of 3 falls back to two steps per launch."""
+    media = [_seam_medium(43, nt=101, n_tx=5), W.small_random_medium(44, 90, 66, 80, n_tx=2, n_rcv=4, npml=3)]
+    obs = [_observed(m, 60 + i) for i, m in enumerate(media)]
+    res, plan = gpu_run(media, obs, dtype="f32", ckpt=6, steps_per_launch=3)
+    assert plan.info["steps_per_launch"] == 3
+    for m, o, r in zip(media, obs, res):
+        _check(r, oracle_grad(m, o), "f32")
+    res, plan = gpu_run(media, obs, dtype="f32", ckpt=7, steps_per_launch=3)
+    assert plan.info["steps_per_launch"] == 2
+    for m, o, r in zip(media, obs, res):
+        _check(r, oracle_grad(m, o), "f32")
+
+
+@pytest.mark.parametrize("spl", [1, 2, 3])
 def test_forward_only_plan(spl):
     """A forward-only plan (rolling four-plane buffer, no replay) gives
     bitwise the traces and misfit of a full plan and refuses gradients."""
@@ -276,7 +321,8 @@ def test_autotune_choice_and_cache(tmp_path):
     grids = [F.GridSpec.of(m.geom, float(m.c.max()) * 1.0001) for m in media]
     cache = str(tmp_path / "tune.json")
     a = F.autotune(grids, dtype="f32", cache=cache)
-    assert (a["steps_per_launch"], a["rows"]) in {(2, 1), (2, 2), (2, 4), (1, 2), (1, 4), (1, 8)}
+    assert (a["steps_per_launch"], a["rows"]) in {(3, 1), (3, 2), (3, 4), (2, 1), (2, 2), (2, 4), (1, 2), (1, 4),
+                                                  (1, 8)}
     assert a["group"] in (1, 2, 4)
     assert a["ns_per_update"] > 0
     entries = json.load(open(cache))

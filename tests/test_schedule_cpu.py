@@ -25,25 +25,25 @@ def dump():
     r = subprocess.run(cmd, capture_output=True, text=True)
     assert r.returncode == 0, r.stderr[-2000:]
 
-    def run(T, K, S):
-        out = subprocess.run([exe, str(T), str(K), str(S)], capture_output=True, text=True, check=True).stdout
+    def run(T, K, S, Sa):
+        out = subprocess.run([exe, str(T), str(K), str(S), str(Sa)], capture_output=True, text=True, check=True).stdout
         return [tuple(int(v) for v in l.split()) for l in out.splitlines()]
     return run
 
 
-CASES = [(T, K, S) for S in (1, 2) for T, K in
+CASES = [(T, K, S, Sa) for S, Sa in ((1, 1), (2, 2), (3, 2)) for T, K in
          [(1, 1), (2, 2), (3, 3), (5, 2), (7, 3), (10, 4), (11, 4), (64, 8), (65, 8), (100, 14), (101, 14),
-          (120, 120), (37, 36), (4000, 90), (3407, 82)]]
+          (120, 120), (37, 36), (4000, 90), (3407, 82), (100, 12), (4000, 84)]]
 
 
-@pytest.mark.parametrize("T,K,S", CASES)
-def test_schedule(dump, T, K, S):
+@pytest.mark.parametrize("T,K,S,Sa", CASES)
+def test_schedule(dump, T, K, S, Sa):
     K = min(K, T)
     J = (T + K - 1) // K
     last = T - (J - 1) * K
-    seq = dump(T, K, S)
+    seq = dump(T, K, S, Sa)
     # launch count of the host plan
-    steps = -(-T // S) + -(-last // S) + 2 * (-(-K // S)) * (J - 1)
+    steps = -(-T // S) + -(-last // Sa) + (-(-K // S) + -(-K // Sa)) * (J - 1)
     assert len(seq) == steps
     i = 0
     # forward: steps 0..T-1 in order, runs of S
@@ -61,7 +61,7 @@ def test_schedule(dump, T, K, S):
         lev = top
         while lev >= bottom:
             ph, t, j, c = seq[i]
-            assert ph == 3 and t == lev + 1 and 1 <= c <= S and lev - c + 1 >= bottom
+            assert ph == 3 and t == lev + 1 and 1 <= c <= Sa and lev - c + 1 >= bottom
             lev -= c
             i += 1
         assert lev == bottom - 1
