@@ -333,7 +333,8 @@ def main():
         "roofline": {
             "bound": "hbm",
             "kernel": ("step kernels (fwd4_kernel, adj4_kernel): 24 B per update each" if args.order == 4 else
-                       "step kernels (fwd2_kernel, adj2_kernel, fwd1_kernel, adj1_kernel): 24 B per update each"),
+                       "step kernels (fwd3_kernel, fwd2_kernel, adj2_kernel, fwd1_kernel, adj1_kernel): "
+                       "24 B per update each"),
             "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
@@ -383,13 +384,16 @@ def load_traffic(info, launches):
     """HBM bytes per step-kernel launch: the bytes per executed cell-update
     measured by the committed rocprofv3 counter runs (FETCH_SIZE, WRITE_SIZE,
     scaled by a 1 GiB copy) times this workload's executed updates per
-    launch; null when the kernel source differs from the one measured."""
+    launch; null when the kernel source differs from the one measured or the
+    plan fuses a different number of steps or rows per launch."""
     path = os.path.join(ROOT, "profiles", "step_kernel_traffic.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
     src = open(os.path.join(ROOT, "paper_2603_04070_amd", "csrc", "fwi_kernels.hpp"), "rb").read()
     if rec.get("kernel_source_sha256") != hashlib.sha256(src).hexdigest():
+        return None
+    if (rec.get("steps_per_launch"), rec.get("rows")) != (info["steps_per_launch"], info["rows"]):
         return None
     executed = info["cell_updates"] + info["recompute_updates"]
     return int(rec["bytes_per_executed_update"] * executed / launches)
