@@ -110,6 +110,8 @@ def _grid(**kw):
     ({}, dict(order=4, persistent=True), 1),
     ({}, dict(order=4, steps_per_launch=2), 1),
     ({}, dict(order=4, rows=8), 1),
+    (dict(nx=20000, nz=20000), {}, 1),                      # a field plane of 4 transmits >= 4 GiB
+    (dict(nx=12000, nz=12000), dict(dtype="f64"), 1),       # FP64: 144e6 cells x 4 x 8 B >= 4 GiB
 ])
 def test_host_validation(kw, opt, code):
     with pytest.raises(F.FwiError) as e:
