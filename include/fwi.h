@@ -106,10 +106,9 @@ typedef struct fwi_options {
     int32_t acc_double;      /* 1: imaging accumulators in double for FWI_F32 (default 0)       */
     int32_t steps_per_launch;/* forward-type time steps fused per launch: 0 = default (3 batched, */
                              /*    2 persistent, 1 plain), 1, 2 or 3.  Adjoint launches fuse     */
-                             /*    min(this, 2) steps.  3 falls back to 2 when a replayed item's */
-                             /*    K is not a multiple of 3 (the automatic K is a multiple of 6); */
-                             /*    2 or 3 fall back to 1 when a wrapping segment buffer has K < 4; */
-                             /*    with 2 or 3, rows must be 1, 2 or 4; 3 is not persistent      */
+                             /*    min(this, 2) steps.  2 or 3 fall back to 1 when a wrapping    */
+                             /*    segment buffer has K < 4; with 2 or 3, rows must be 1, 2 or 4; */
+                             /*    3 is not persistent                                           */
     int32_t forward_only;    /* 1: traces and misfit only; no replay state is kept and           */
                              /*    gradient or adjoint calls return FWI_ERR_INVALID              */
     int32_t persistent;      /* 1: one launch per wave runs every step, its workgroups meeting   */

@@ -367,17 +367,21 @@ __device__ __forceinline__ const T* fwd_plane(const Item<T, Acc>& it, const Step
     return it.seg + (int64_t)((tau - 1) % it.K) * it.plane;
 }
 
-// v slot of level tau.  A launch of two or more steps reads v^n at other
-// tiles' cells, so it must write v^{n+c} to the other slot.  With at most two
-// steps per launch, slot floor(tau/2) mod 2: a two-step launch starts at an
-// even level (K is even).  With three, slot ceil(tau/3) mod 2: launches start
-// at multiples of 3 (K is a multiple of 3), so a launch of 2 or 3 steps flips
-// the slot.  A one-step launch reads and writes each cell's own value, in
-// place or across slots.
+// v slot of level tau in a run of forward-type launches.  A launch of two or
+// more steps reads v^n at other tiles' cells, so it must write v^{n+c} to
+// the other slot.  With at most two steps per launch, slot floor(tau/2) mod
+// 2: a run's launches start two levels apart, so every two-step launch flips
+// it.  With three, slot ceil((tau - base)/3) mod 2 with base the run's first
+// level (0 for the first pass, jK for the recompute of segment j): launches
+// start at base + 3m, and one of 2 or 3 steps (a run's last launch may be
+// shorter) ends in the other slot.  A one-step launch reads and writes each
+// cell's own value, in place or across slots.
 template <typename T, typename Acc>
-__device__ __forceinline__ int vel_slot(const Item<T, Acc>& it, int tau)
+__device__ __forceinline__ int vel_slot(const Item<T, Acc>& it, const Step& st, int tau)
 {
-    return it.S == 3 ? ((tau + 2) / 3) & 1 : (tau >> 1) & 1;
+    if (it.S != 3) return (tau >> 1) & 1;
+    const int base = st.phase == kRecomp ? st.j * it.K : 0;
+    return ((tau - base + 2) / 3) & 1;
 }
 
 // Plane of v^tau read by a forward-type step: zero for tau = 0; on
@@ -387,13 +391,13 @@ __device__ __forceinline__ const T* vel_in(const Item<T, Acc>& it, const Step& s
 {
     if (tau <= 0) return it.zero;
     if (st.phase == kRecomp && tau == st.j * it.K) return it.ck + (int64_t)(2 * (st.j - 1)) * it.plane;
-    return it.vel + (int64_t)vel_slot(it, tau) * it.plane;
+    return it.vel + (int64_t)vel_slot(it, st, tau) * it.plane;
 }
 
 template <typename T, typename Acc>
-__device__ __forceinline__ T* vel_out(const Item<T, Acc>& it, int tau)
+__device__ __forceinline__ T* vel_out(const Item<T, Acc>& it, const Step& st, int tau)
 {
-    return it.vel + (int64_t)vel_slot(it, tau) * it.plane;
+    return it.vel + (int64_t)vel_slot(it, st, tau) * it.plane;
 }
 
 // Checkpoint pair that level t1 = jK (1 <= j <= J-1, the start of segment j)
@@ -522,7 +526,7 @@ __device__ void tile_forward(const Item<T, Acc>& it, const Step& st, int tile_x,
     const T* cur = fwd_plane(it, st, n);
     const T* vin = vel_in(it, st, n);
     T* out = it.seg + (int64_t)(n % it.K) * it.plane;
-    T* vout = vel_out(it, n + 1);
+    T* vout = vel_out(it, st, n + 1);
     T* ckv = ckpt_pair(it, st, n + 1);
     T* cku = ckv ? ckv + it.plane : nullptr;
     const Src<T, G> src = sources<T, G>(it, n);
@@ -731,7 +735,7 @@ __device__ void tile_forward2(const Item<T, Acc>& it, const Step& st, int tile_x
     const T* vin = vel_in(it, st, n);
     T* out1 = it.seg + (int64_t)(n % it.K) * it.plane;
     T* out2 = it.seg + (int64_t)((n + 1) % it.K) * it.plane;
-    T* vout = vel_out(it, n + 2);
+    T* vout = vel_out(it, st, n + 2);
     T* ck1 = ckpt_pair(it, st, n + 1);
     T* ck2 = ckpt_pair(it, st, n + 2);
     // u^{n+1} is the next launch's input only when this launch stops there;
@@ -935,7 +939,7 @@ __device__ void tile_forward3(const Item<T, Acc>& it, const Step& st, int tile_x
     T* out1 = it.seg + (int64_t)(n % it.K) * it.plane;
     T* out2 = it.seg + (int64_t)((n + 1) % it.K) * it.plane;
     T* out3 = it.seg + (int64_t)((n + 2) % it.K) * it.plane;
-    T* vout = vel_out(it, n + 3);
+    T* vout = vel_out(it, st, n + 3);
     T* ck1 = ckpt_pair(it, st, n + 1);
     T* ck2 = ckpt_pair(it, st, n + 2);
     T* ck3 = ckpt_pair(it, st, n + 3);
@@ -1574,7 +1578,7 @@ __device__ void tile_forward4(const Item<T, Acc>& it, const Step& st, int tile_x
     const T* cur = fwd_plane(it, st, n);
     const T* vin = vel_in(it, st, n);
     T* out = it.seg + (int64_t)(n % it.K) * it.plane;
-    T* vout = vel_out(it, n + 1);
+    T* vout = vel_out(it, st, n + 1);
     T* ckv = ckpt_pair(it, st, n + 1);
     const Src<T, G> src = sources<T, G>(it, n);
     const Span rcv = sample ? span_of(it.tile_off, tile_z * it.tiles_x + tile_x) : Span{0, 0};

@@ -577,7 +577,7 @@ static fwi_status create_impl(fwi_plan* p, fwi_dtype dtype, const fwi_grid* grid
         if (T <= 2) return T;
         int K = (int)std::lround(std::sqrt(2.0 * T));
         // an even K lets two-step launches tile every segment exactly; with
-        // three forward steps per launch K is a multiple of 6
+        // three forward steps per launch a multiple of 6 lets both kinds do so
         if (p->S == 2 && K % 2) ++K;
         if (p->S == 3 && K % 6) K += 6 - K % 6;
         return std::max(2, std::min(K, T));
@@ -661,13 +661,6 @@ static fwi_status create_impl(fwi_plan* p, fwi_dtype dtype, const fwi_grid* grid
             if (!w.items.empty()) p->waves.push_back(w);
         }
     }
-    // three forward steps per launch: recompute runs must start at multiples
-    // of 3 (the v slot rule), so K is a multiple of 3 wherever there is replay
-    if (p->S == 3)
-        for (auto& it : p->items) {
-            const int T = p->media[it.medium].g.nt;
-            if (it.K < T && !o.forward_only && it.K % 3) p->S = 2;
-        }
     // a launch of two or three steps reads and writes up to four field planes
     // of the segment buffer at once: that needs K >= 4 wherever the buffer wraps
     if (p->S >= 2)

@@ -212,7 +212,8 @@ def test_two_step_uneven_and_split():
 # ---------------------------------------------------------------- three forward steps per launch
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
-@pytest.mark.parametrize("ckpt,rows,nt", [(0, 2, 100), (9, 2, 101), (10**6, 1, 101), (6, 1, 100), (12, 4, 99)])
+@pytest.mark.parametrize("ckpt,rows,nt", [(0, 2, 100), (9, 2, 101), (10**6, 1, 101), (6, 1, 100), (12, 4, 99),
+                                          (7, 2, 100), (11, 1, 101)])
 def test_three_step_launches(dtype, ckpt, rows, nt):
     """Three forward-type steps per launch (two adjoint steps): parity with
     the oracle on a medium whose sources and receivers sit on tile seams,
@@ -232,26 +233,27 @@ def test_three_step_bitwise_two_step_and_store_all():
     m = W.small_random_medium(42, 97, 70, 121, n_tx=4, n_rcv=6, npml=3)
     obs = _observed(m, 8)
     ref, _ = gpu_run([m], [obs], dtype="f32", ckpt=10**6, steps_per_launch=2)
-    for K in (10**6, 9, 6, 0):
+    for K in (10**6, 9, 6, 0, 7, 8, 10):
         res, plan = gpu_run([m], [obs], dtype="f32", ckpt=K, steps_per_launch=3)
         assert plan.info["steps_per_launch"] == 3
         for k in ("traces", "grad_c", "grad_rho", "misfit"):
             assert np.array_equal(res[0][k], ref[0][k]), (K, k)
 
 
-def test_three_step_uneven_media_and_fallback():
-    """Uneven media in one three-step plan pass parity; an interval that is
-    not a multiple of 3 falls back to two steps per launch."""
+def test_three_step_uneven_media_any_interval():
+    """Uneven media in one three-step plan pass parity, also with an interval
+    that is not a multiple of 3 (recompute runs end in a shorter launch)."""
     media = [_seam_medium(43, nt=101, n_tx=5), W.small_random_medium(44, 90, 66, 80, n_tx=2, n_rcv=4, npml=3)]
     obs = [_observed(m, 60 + i) for i, m in enumerate(media)]
     res, plan = gpu_run(media, obs, dtype="f32", ckpt=6, steps_per_launch=3)
     assert plan.info["steps_per_launch"] == 3
     for m, o, r in zip(media, obs, res):
         _check(r, oracle_grad(m, o), "f32")
-    res, plan = gpu_run(media, obs, dtype="f32", ckpt=7, steps_per_launch=3)
-    assert plan.info["steps_per_launch"] == 2
-    for m, o, r in zip(media, obs, res):
-        _check(r, oracle_grad(m, o), "f32")
+    for K in (7, 8):
+        res, plan = gpu_run(media, obs, dtype="f32", ckpt=K, steps_per_launch=3)
+        assert plan.info["steps_per_launch"] == 3
+        for m, o, r in zip(media, obs, res):
+            _check(r, oracle_grad(m, o), "f32")
 
 
 @pytest.mark.parametrize("spl", [1, 2, 3])
