@@ -323,6 +323,20 @@ __device__ __forceinline__ T adj_cell(T a, T b, T fw, T fe, T fn, T fs, T w0, T 
     return fma(a, l0, fma(b, lp, L));
 }
 
+// The same update in terms of w = q lam (the second-order kernels carry w):
+// w^{t-1} = a w^t + b w^{t+1} + q sum_f b_f (w_f - w0), the lam update
+// multiplied by the cell's q, so no neighbour's q enters.
+template <typename T>
+__device__ __forceinline__ T adjw_cell(T a, T b, T q, T fw, T fe, T fn, T fs, T w0, T ww, T we, T wn, T ws, T wp)
+{
+#pragma clang fp contract(off)
+    T L = fw * (ww - w0);
+    L = fma(fe, we - w0, L);
+    L = fma(fn, wn - w0, L);
+    L = fma(fs, ws - w0, L);
+    return fma(a, w0, fma(b, wp, q * L));
+}
+
 // Zero-lag imaging terms of one cell: S_kappa += l0 sum_f b_f du_f,
 // S_b += sum_f c_f du_f dw_f (c_f = 1/2 on interior faces, 1 on border faces).
 template <typename T>
@@ -495,8 +509,9 @@ __device__ __forceinline__ bool has_adj_source(const Item<T, Acc>& it)
 }
 
 // Add the adjoint source of sample m to field plane ``f`` at the receivers of
-// one tile (one thread per run of equal slots, entries of a run in order).
-template <typename T, typename Acc>
+// one tile (one thread per run of equal slots, entries of a run in order);
+// W: the plane holds w = q lam, so the source is scaled by the cell's q.
+template <bool W, int G, typename T, typename Acc>
 __device__ __forceinline__ void inject_tile(const Item<T, Acc>& it, Span sp, int m, T* f)
 {
     if (sp.e1 <= sp.e0 || m < 0 || !has_adj_source(it)) return;
@@ -507,6 +522,7 @@ __device__ __forceinline__ void inject_tile(const Item<T, Acc>& it, Span sp, int
         if (en.run == 0) continue;
         T s = T(0);
         for (int k = 0; k < en.run; ++k) s += adj_source(it, ld_entry(it.entries, e + k), m);
+        if (W) s = ldg(it.coef, 2 * (int64_t)(en.slot / G)) * s;
         stg(f, en.slot, ldg(f, en.slot) + s);
     }
 }
@@ -584,9 +600,9 @@ __device__ void tile_adjoint(const Item<T, Acc>& it, const Step& st, int tile_x,
 {
     const int nx = it.nx, nz = it.nz, t = st.n;
     const int64_t P = it.plane, ncell = (int64_t)nx * nz;
-    const T* cur = it.lam + (int64_t)(t % it.nlam) * P;          // lam^t
-    const T* p1 = it.lam + (int64_t)((t + 1) % it.nlam) * P;     // lam^{t+1}
-    T* out = it.lam + (int64_t)((t - 1) % it.nlam) * P;          // lam^{t-1} (in place when nlam = 2)
+    const T* cur = it.lam + (int64_t)(t % it.nlam) * P;          // w^t = q lam^t
+    const T* p1 = it.lam + (int64_t)((t + 1) % it.nlam) * P;     // w^{t+1}
+    T* out = it.lam + (int64_t)((t - 1) % it.nlam) * P;          // w^{t-1} (in place when nlam = 2)
     const T* um = it.seg + (int64_t)((t - 2) % it.K) * P;        // u^{t-1}
     Acc* accK = it.acc;
     Acc* accB = it.acc + ncell;
@@ -605,7 +621,6 @@ __device__ void tile_adjoint(const Item<T, Acc>& it, const Step& st, int tile_x,
         Vec<T, G> lc = vload<T, G>(cur, x);
         Vec<T, G> uN = iz > 0 ? vload<T, G>(um, x - nx) : vzero<T, G>();
         Vec<T, G> uC = vload<T, G>(um, x);
-        T qn = iz > 0 ? ldg(cf, 2 * (x - nx)) : T(0);
         T bn = iz > 0 ? ldg(cf, 2 * (x - nx) + 1) : T(0);
         T qc = ldg(cf, 2 * x), bc = ldg(cf, 2 * x + 1);
         const int zend = min(z0 + rows, nz);
@@ -619,9 +634,7 @@ __device__ void tile_adjoint(const Item<T, Acc>& it, const Step& st, int tile_x,
             const Vec<T, G> le = he ? vload<T, G>(cur, x + 1) : vzero<T, G>();
             const Vec<T, G> uW = hw ? vload<T, G>(um, x - 1) : vzero<T, G>();
             const Vec<T, G> uE = he ? vload<T, G>(um, x + 1) : vzero<T, G>();
-            const T qw = hw ? ldg(cf, 2 * (x - 1)) : T(0);
             const T bw = hw ? ldg(cf, 2 * (x - 1) + 1) : T(0);
-            const T qe = he ? ldg(cf, 2 * (x + 1)) : T(0);
             const T be = he ? ldg(cf, 2 * (x + 1) + 1) : T(0);
             T fw, fe, fn, fs;
             faces<T>(hw, he, hn, hs, bc, bw, be, bn, bs, fw, fe, fn, fs);
@@ -631,14 +644,14 @@ __device__ void tile_adjoint(const Item<T, Acc>& it, const Step& st, int tile_x,
             const Vec<T, G> lp = vload<T, G>(p1, x);
             Vec<T, G> r;
             Acc sk = Acc(0), sb = Acc(0);
+            // the planes hold w = q lam: the kappa imaging term w0 sum_f b_f du_f
+            // is q times the lam one (undone per cell when the gradient is formed)
 #pragma unroll
             for (int g = 0; g < G; ++g) {
-                const T w0 = qc * lc.v[g], ww = qw * lw.v[g], we = qe * le.v[g];
-                const T wn = qn * ln.v[g], ws = qs * ls.v[g];
-                r.v[g] = adj_cell<T>(a, b, fw, fe, fn, fs, w0, ww, we, wn, ws, lc.v[g], lp.v[g]);
+                r.v[g] = adjw_cell<T>(a, b, qc, fw, fe, fn, fs, lc.v[g], lw.v[g], le.v[g], ln.v[g], ls.v[g], lp.v[g]);
                 T k1, b1;
-                image_cell<T>(fw, fe, fn, fs, cw, ce, cn, cs, lc.v[g], w0, ww, we, wn, ws, uC.v[g], uW.v[g],
-                              uE.v[g], uN.v[g], uS.v[g], k1, b1);
+                image_cell<T>(fw, fe, fn, fs, cw, ce, cn, cs, lc.v[g], lc.v[g], lw.v[g], le.v[g], ln.v[g], ls.v[g],
+                              uC.v[g], uW.v[g], uE.v[g], uN.v[g], uS.v[g], k1, b1);
                 sk += Acc(k1);
                 sb += Acc(b1);
             }
@@ -646,11 +659,11 @@ __device__ void tile_adjoint(const Item<T, Acc>& it, const Step& st, int tile_x,
             stg(accK, x, ldg(accK, x) + sk);
             stg(accB, x, ldg(accB, x) + sb);
             ln = lc; lc = ls; uN = uC; uC = uS;
-            qn = qc; qc = qs; bn = bc; bc = bs;
+            qc = qs; bn = bc; bc = bs;
         }
     }
-    // adjoint source of lam^{t-1}: sample t-2
-    inject_tile(it, span_of(it.tile_off, tile_z * it.tiles_x + tile_x), t - 2, out);
+    // adjoint source of w^{t-1}: q times sample t-2
+    inject_tile<true, G>(it, span_of(it.tile_off, tile_z * it.tiles_x + tile_x), t - 2, out);
 }
 
 // ============================================================== two steps per launch
@@ -1104,11 +1117,13 @@ __device__ void tile_adjoint2(const Item<T, Acc>& it, const Step& st, int tile_x
     using L = Lds2<T, G, R, true>;
     const int nx = it.nx, nz = it.nz, t = st.n, nl = it.nlam;
     const int64_t P = it.plane, ncell = (int64_t)nx * nz;
-    Vec<T, G>* L0 = reinterpret_cast<Vec<T, G>*>(smem);                  // lam^t, tile + 2
+    // The adjoint planes hold w = q lam (adjw_cell); "lam" below names the
+    // level, the values are w.
+    Vec<T, G>* L0 = reinterpret_cast<Vec<T, G>*>(smem);                  // w^t, tile + 2
     T* Q0 = reinterpret_cast<T*>(L0 + L::N0);                            // q, tile + 2
     T* B0 = Q0 + L::N0;                                                  // bt, tile + 2
     // two tile + 1 planes without their first and last (corner) cells: X holds
-    // u^{t-1} for the imaging of (lam^t, u^{t-1}), then lam^{t-1}; Y holds u^{t-2}
+    // u^{t-1} for the imaging of (lam^t, u^{t-1}), then w^{t-1}; Y holds u^{t-2}
     Vec<T, G>* X = reinterpret_cast<Vec<T, G>*>(B0 + L::N0) - 1;
     Vec<T, G>* Y = X + (L::N1 - 2);
     T* D = reinterpret_cast<T*>(Y + (L::N1 - 1));                        // damping
@@ -1200,13 +1215,12 @@ __device__ void tile_adjoint2(const Item<T, Acc>& it, const Step& st, int tile_x
                 faces<T>(ix1 > 0, ix1 < nx - 1, iz1 > 0, iz1 < nz - 1, B0[k], B0[k - 1],
                          B0[k + 1], B0[k - L::W0], B0[k + L::W0], fw, fe, fn, fs);
                 damp_coeffs<T>(D[ex + 1] + D[L::W0 + ez + 1], a, b);
-                const T qc = Q0[k], qw = Q0[k - 1], qe = Q0[k + 1], qn = Q0[k - L::W0],
-                        qs = Q0[k + L::W0];
+                const T qc = Q0[k];
                 const Vec<T, G> l0 = L0[k], lw = L0[k - 1], le = L0[k + 1], ln = L0[k - L::W0], ls = L0[k + L::W0];
 #pragma unroll
                 for (int g = 0; g < G; ++g)
-                    m1[i].v[g] = adj_cell<T>(a, b, fw, fe, fn, fs, qc * l0.v[g], qw * lw.v[g], qe * le.v[g],
-                                             qn * ln.v[g], qs * ls.v[g], l0.v[g], pv[i].v[g]);
+                    m1[i].v[g] = adjw_cell<T>(a, b, qc, fw, fe, fn, fs, l0.v[g], lw.v[g], le.v[g], ln.v[g],
+                                              ls.v[g], pv[i].v[g]);
             }
         }
     }
@@ -1227,15 +1241,14 @@ __device__ void tile_adjoint2(const Item<T, Acc>& it, const Step& st, int tile_x
             T fw, fe, fn, fs;
             faces<T>(hw, he, hn, hs, B0[k0], B0[k0 - 1], B0[k0 + 1], B0[k0 - L::W0], B0[k0 + L::W0], fw, fe, fn, fs);
             const T cn = hn ? hf : T(1), cs = hs ? hf : T(1);
-            const T qc = Q0[k0], qw = Q0[k0 - 1], qe = Q0[k0 + 1], qn = Q0[k0 - L::W0], qs = Q0[k0 + L::W0];
             const Vec<T, G> l0 = L0[k0], lw = L0[k0 - 1], le = L0[k0 + 1], ln = L0[k0 - L::W0],
                             ls = L0[k0 + L::W0];
             const Vec<T, G> a0 = X[k1], aw = X[k1 - 1], ae = X[k1 + 1], an = X[k1 - L::W1], as = X[k1 + L::W1];
 #pragma unroll
             for (int g = 0; g < G; ++g) {
                 T k1a, b1a;
-                image_cell<T>(fw, fe, fn, fs, cw, ce, cn, cs, l0.v[g], qc * l0.v[g], qw * lw.v[g], qe * le.v[g],
-                              qn * ln.v[g], qs * ls.v[g], a0.v[g], aw.v[g], ae.v[g], an.v[g], as.v[g], k1a, b1a);
+                image_cell<T>(fw, fe, fn, fs, cw, ce, cn, cs, l0.v[g], l0.v[g], lw.v[g], le.v[g], ln.v[g], ls.v[g],
+                              a0.v[g], aw.v[g], ae.v[g], an.v[g], as.v[g], k1a, b1a);
                 ska[k] += Acc(k1a);
                 sba[k] += Acc(b1a);
             }
@@ -1248,8 +1261,9 @@ __device__ void tile_adjoint2(const Item<T, Acc>& it, const Step& st, int tile_x
         if (c > 0 && c < L::N1 - 1) X[c] = m1[i];
     }
     __syncthreads();
-    // adjoint source of lam^{t-1} (sample t-2) at the receivers of the grown
-    // tile (the two corner cells that X does not hold are read by no tile cell)
+    // adjoint source of lam^{t-1} (sample t-2, times q) at the receivers of
+    // the grown tile (the two corner cells that X does not hold are read by
+    // no tile cell)
     if (rcv_x.e1 > rcv_x.e0 && has_adj_source(it)) {
         for (int e = rcv_x.e0 + tid; e < rcv_x.e1; e += kBlock) {
             const Entry en = ld_entry(it.entries_x, e);
@@ -1259,7 +1273,7 @@ __device__ void tile_adjoint2(const Item<T, Acc>& it, const Step& st, int tile_x
             const int cell = en.slot / G, g = en.slot - cell * G;
             const int ex = cell % nx - (x0 - 1), ez = cell / nx - (z0 - 1);
             const int c = ez * L::W1 + ex;
-            if (c > 0 && c < L::N1 - 1) X[c].v[g] += sum;
+            if (c > 0 && c < L::N1 - 1) X[c].v[g] += Q0[(ez + 1) * L::W0 + ex + 1] * sum;
         }
         __syncthreads();
     }
@@ -1279,8 +1293,7 @@ __device__ void tile_adjoint2(const Item<T, Acc>& it, const Step& st, int tile_x
                          B0[k0 - L::W0], B0[k0 + L::W0], fw, fe, fn, fs);
                 const T cn = hn ? hf : T(1), cs = hs ? hf : T(1);
                 damp_coeffs<T>(exd + D[L::W0 + ez + 2], a, b);
-                const T qc = Q0[k0], qw = Q0[k0 - 1], qe = Q0[k0 + 1], qn = Q0[k0 - L::W0],
-                        qs = Q0[k0 + L::W0];
+                const T qc = Q0[k0];
                 const Vec<T, G> l0 = L0[k0];
                 const Vec<T, G> m0 = X[k1], mw = X[k1 - 1], me = X[k1 + 1], mn = X[k1 - L::W1],
                                 ms = X[k1 + L::W1];
@@ -1290,12 +1303,11 @@ __device__ void tile_adjoint2(const Item<T, Acc>& it, const Step& st, int tile_x
                 Acc skb = Acc(0), sbb = Acc(0);
 #pragma unroll
                 for (int g = 0; g < G; ++g) {
-                    const T v0 = qc * m0.v[g], vw = qw * mw.v[g], ve = qe * me.v[g], vn = qn * mn.v[g],
-                            vs = qs * ms.v[g];
-                    r.v[g] = adj_cell<T>(a, b, fw, fe, fn, fs, v0, vw, ve, vn, vs, m0.v[g], l0.v[g]);
+                    r.v[g] = adjw_cell<T>(a, b, qc, fw, fe, fn, fs, m0.v[g], mw.v[g], me.v[g], mn.v[g], ms.v[g],
+                                          l0.v[g]);
                     T k1b, b1b;
-                    image_cell<T>(fw, fe, fn, fs, cw, ce, cn, cs, m0.v[g], v0, vw, ve, vn, vs, c0.v[g], cw2.v[g],
-                                  ce2.v[g], cn2.v[g], cs2.v[g], k1b, b1b);
+                    image_cell<T>(fw, fe, fn, fs, cw, ce, cn, cs, m0.v[g], m0.v[g], mw.v[g], me.v[g], mn.v[g],
+                                  ms.v[g], c0.v[g], cw2.v[g], ce2.v[g], cn2.v[g], cs2.v[g], k1b, b1b);
                     skb += Acc(k1b);
                     sbb += Acc(b1b);
                 }
@@ -1313,8 +1325,8 @@ __device__ void tile_adjoint2(const Item<T, Acc>& it, const Step& st, int tile_x
             }
         }
     }
-    // adjoint source of lam^{t-2}: sample t-3
-    inject_tile(it, rcv, t - 3, out2);
+    // adjoint source of lam^{t-2}: sample t-3, times q
+    inject_tile<true, G>(it, rcv, t - 3, out2);
 }
 
 // Item position at launch s of a call (mode shifts / limits the schedule).
@@ -1697,7 +1709,7 @@ __device__ void tile_adjoint4(const Item<T, Acc>& it, const Step& st, int tile_x
         }
     }
     // adjoint source of lam^{t-1}: sample t-2
-    inject_tile(it, rcv, t - 2, out);
+    inject_tile<false, G>(it, rcv, t - 2, out);
 }
 
 template <typename T, int G, typename Acc, int R>
@@ -1831,7 +1843,7 @@ struct MediumDev {
     double* misfit;
     const void* acc0;                 // first accumulator slot of the medium
     int32_t acc_slots;
-    int32_t pad3;
+    int32_t acc_q;                    // 1: the kappa accumulators hold q times the imaging sum
 };
 
 __device__ __forceinline__ double dprof(int i, int n, int N, double dmax)
@@ -1948,6 +1960,9 @@ __global__ void finalize_kernel(const MediumDev<T>* __restrict__ media, unsigned
         const int ix = (int)(x % m.nx), iz = (int)(x / m.nx);
         const double e = (dprof(ix, m.nx, m.npml, m.dmax) + dprof(iz, m.nz, m.npml, m.dmax)) * m.dt;
         const double gam = m.dt * m.dt / (1.0 + e);
+        // the second-order kernels carry w = q lam, so their kappa sum is q
+        // times the lam one, q the stored coefficient they multiplied by
+        if (m.acc_q) sk /= (double)m.coef[2 * x];
         const double gk = gam / (m.h * m.h * kRhoRef) * sk;
         const double gb = -kRhoRef * sb;
         const double c = (double)m.c[x], rho = (double)m.rho[x];
