@@ -1471,8 +1471,9 @@ __device__ __forceinline__ void lap4_axis(const Vec<T, G>* V, const T* C, int k,
 }
 
 // Adjoint work of one axis at LDS cell k (position i of n along the axis),
-// from one read of the seven lambda^t, u^{t-1} and q values and five bt
-// around it: Lw += operator of w = q lambda, Lu += operator of u, and the
+// from one read of the seven w^t = q lambda^t and u^{t-1} values and five bt
+// around it: Lw += flux operator of w (the cell's q is applied by the
+// caller), Lu += operator of u, and the
 // imaging share sb += sum over the faces whose bt involve the cell of its
 // part of (D u)_f (D w)_f: half of each neighbouring face, the whole face
 // where the neighbour is a ghost repeating this cell, and the face between
@@ -1482,12 +1483,11 @@ __device__ __forceinline__ void adj4_axis(const Vec<T, G>* Lm, const Vec<T, G>* 
                                           int n, Vec<T, G>& Lw, Vec<T, G>& Lu, Acc& sb)
 {
     Vec<T, G> l[7], u[7];
-    T q[7], bt[5];
+    T bt[5];
 #pragma unroll
     for (int j = 0; j < 7; ++j) {
         l[j] = Lm[k + (j - 3) * s];
         u[j] = U[k + (j - 3) * s];
-        q[j] = C[2 * (k + (j - 3) * s)];
     }
 #pragma unroll
     for (int j = 0; j < 5; ++j) bt[j] = C[2 * (k + (j - 2) * s) + 1];
@@ -1501,7 +1501,7 @@ __device__ __forceinline__ void adj4_axis(const Vec<T, G>* Lm, const Vec<T, G>* 
         T w[7], v[7];
 #pragma unroll
         for (int j = 0; j < 7; ++j) {
-            w[j] = q[j] * l[j].v[g];
+            w[j] = l[j].v[g];
             v[j] = u[j].v[g];
         }
         const T dw3 = d4<T>(w[0], w[1], w[2], w[3]), dw1 = d4<T>(w[1], w[2], w[3], w[4]);
@@ -1650,12 +1650,15 @@ __device__ void tile_adjoint4(const Item<T, Acc>& it, const Step& st, int tile_x
     using L = Lds4<T, G, R, true>;
     const int nx = it.nx, nz = it.nz, t = st.n;
     const int64_t P = it.plane, ncell = (int64_t)nx * nz;
-    Vec<T, G>* Lm = reinterpret_cast<Vec<T, G>*>(smem);                 // lam^t
+    // the planes hold w = q lam, as for the second-order operator: w^{t-1} =
+    // a w^t + b w^{t+1} + q (flux terms of w), and the kappa term w^t L u is q
+    // times the lambda one (undone when the gradient is formed)
+    Vec<T, G>* Lm = reinterpret_cast<Vec<T, G>*>(smem);                 // w^t
     Vec<T, G>* U = Lm + L::N;                                           // u^{t-1}
     T* C = reinterpret_cast<T*>(U + L::N);
-    const T* cur = it.lam + (int64_t)(t % it.nlam) * P;                 // lam^t
-    const T* p1 = it.lam + (int64_t)((t + 1) % it.nlam) * P;            // lam^{t+1}
-    T* out = it.lam + (int64_t)((t - 1) % it.nlam) * P;                 // lam^{t-1}
+    const T* cur = it.lam + (int64_t)(t % it.nlam) * P;                 // w^t
+    const T* p1 = it.lam + (int64_t)((t + 1) % it.nlam) * P;            // w^{t+1}
+    T* out = it.lam + (int64_t)((t - 1) % it.nlam) * P;                 // w^{t-1}
     const T* um = it.seg + (int64_t)((t - 2) % it.K) * P;               // u^{t-1}
     Acc* accK = it.acc;
     Acc* accB = it.acc + ncell;
@@ -1694,12 +1697,13 @@ __device__ void tile_adjoint4(const Item<T, Acc>& it, const Step& st, int tile_x
                 T a, b;
                 damp_coeffs<T>(exd + ezd[k], a, b);
                 const Vec<T, G> l0 = Lm[kk];
+                const T qc = C[2 * kk];
                 Vec<T, G> r;
                 Acc sk = Acc(0);
 #pragma unroll
                 for (int g = 0; g < G; ++g) {
 #pragma clang fp contract(off)
-                    r.v[g] = fma(a, l0.v[g], fma(b, lp[k].v[g], Lw.v[g]));
+                    r.v[g] = fma(a, l0.v[g], fma(b, lp[k].v[g], qc * Lw.v[g]));
                     sk += Acc(l0.v[g] * Lu.v[g]);
                 }
                 vstore<T, G>(out, x, r);
@@ -1708,8 +1712,8 @@ __device__ void tile_adjoint4(const Item<T, Acc>& it, const Step& st, int tile_x
             }
         }
     }
-    // adjoint source of lam^{t-1}: sample t-2
-    inject_tile<false, G>(it, rcv, t - 2, out);
+    // adjoint source of w^{t-1}: q times sample t-2
+    inject_tile<true, G>(it, rcv, t - 2, out);
 }
 
 template <typename T, int G, typename Acc, int R>
@@ -1843,7 +1847,7 @@ struct MediumDev {
     double* misfit;
     const void* acc0;                 // first accumulator slot of the medium
     int32_t acc_slots;
-    int32_t acc_q;                    // 1: the kappa accumulators hold q times the imaging sum
+    int32_t pad3;
 };
 
 __device__ __forceinline__ double dprof(int i, int n, int N, double dmax)
@@ -1960,9 +1964,9 @@ __global__ void finalize_kernel(const MediumDev<T>* __restrict__ media, unsigned
         const int ix = (int)(x % m.nx), iz = (int)(x / m.nx);
         const double e = (dprof(ix, m.nx, m.npml, m.dmax) + dprof(iz, m.nz, m.npml, m.dmax)) * m.dt;
         const double gam = m.dt * m.dt / (1.0 + e);
-        // the second-order kernels carry w = q lam, so their kappa sum is q
-        // times the lam one, q the stored coefficient they multiplied by
-        if (m.acc_q) sk /= (double)m.coef[2 * x];
+        // the adjoint kernels carry w = q lam, so the kappa sum is q times
+        // the lam one, q the stored coefficient they multiplied by
+        sk /= (double)m.coef[2 * x];
         const double gk = gam / (m.h * m.h * kRhoRef) * sk;
         const double gb = -kRhoRef * sb;
         const double c = (double)m.c[x], rho = (double)m.rho[x];

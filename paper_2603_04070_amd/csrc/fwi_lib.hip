@@ -1016,7 +1016,6 @@ void fill_descriptors(fwi_plan* p, const fwi_io* io, unsigned char* ws, bool adj
         d.misfit = mio.misfit;
         d.acc0 = ws + m.acc_off;
         d.acc_slots = m.acc_slots;
-        d.acc_q = p->order == 2 ? 1 : 0;
         media[i] = d;
     }
 }
