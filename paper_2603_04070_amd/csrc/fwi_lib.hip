@@ -1359,7 +1359,7 @@ extern "C" fwi_status fwi_autotune(fwi_dtype dtype, const fwi_grid* grids, int32
     }
     TuneChoice best;
     if (ok) {
-        const int cands[][2] = {{3, 1}, {3, 2}, {3, 4}, {2, 1}, {2, 2}, {2, 4}, {1, 2}, {1, 4}, {1, 8}};
+        const int cands[][2] = {{3, 1}, {3, 2}, {3, 4}, {2, 1}, {2, 2}, {2, 4}, {1, 1}, {1, 2}, {1, 4}, {1, 8}};
         hipEvent_t e0, e1;
         (void)hipEventCreate(&e0);
         (void)hipEventCreate(&e1);
