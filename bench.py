@@ -380,13 +380,13 @@ def run_cpu_baseline(media, args, threads=0, seconds=15.0):
             "sample": f"medium 0 ({g.nx}x{g.nz}), {ntx} transmits, first {steps} steps, FP64, d_obs = 0"}
 
 
-def load_traffic(info, launches):
+def load_traffic(info, launches, path=None):
     """HBM bytes per step-kernel launch: the bytes per executed cell-update
     measured by the committed rocprofv3 counter runs (FETCH_SIZE, WRITE_SIZE,
     scaled by a 1 GiB copy) times this workload's executed updates per
     launch; null when the kernel source differs from the one measured or the
     plan fuses a different number of steps or rows per launch."""
-    path = os.path.join(ROOT, "profiles", "step_kernel_traffic.json")
+    path = path or os.path.join(ROOT, "profiles", "step_kernel_traffic.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
