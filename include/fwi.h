@@ -182,8 +182,9 @@ void fwi_plan_destroy(fwi_plan *plan);
 
 /* Autotuner: pick steps_per_launch, rows and (when base->group is 0, for
  * FWI_BATCHED) group for these grids by timing short device probes of every
- * feasible candidate (the grids' schedules cut to 24 steps, every plane kept,
- * a homogeneous medium; groups 4, 2 and 1) and keeping the fastest per
+ * feasible candidate (the grids' schedules cut to 24 steps, or lengthened up
+ * to their own step counts until a call covers about 1e9 cell-updates; every
+ * plane kept, a homogeneous medium; groups 4, 2 and 1) and keeping the fastest per
  * cell-update.  *out receives *base (or the defaults when base is NULL)
  * with those fields set; *ns_per_update (optional) the probe's time.
  * When base->tune_cache names a file, a cached choice for the same GPU

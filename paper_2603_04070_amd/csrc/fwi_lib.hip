@@ -1322,13 +1322,24 @@ extern "C" fwi_status fwi_autotune(fwi_dtype dtype, const fwi_grid* grids, int32
                 return FWI_OK;
             }
 
-    // probe grids: a spread of up to 12 media with their schedules cut to 24 steps
+    // probe grids: a spread of up to 12 media with their schedules cut to 24
+    // steps, or lengthened (up to their own step counts) until one timed call
+    // covers about 1e9 cell-updates, so that small grids are not timed in
+    // the noise of a few launches
     const int n_probe = std::min(n_media, 12);
     std::vector<fwi_grid> pg(n_probe);
+    double work = 0.0;
     for (int i = 0; i < n_probe; ++i) {
         pg[i] = grids[(int64_t)i * n_media / n_probe];
         pg[i].nt = std::min(pg[i].nt, 24);
+        work += 2.0 * pg[i].nx * pg[i].nz * (double)pg[i].n_tx * pg[i].nt;
     }
+    constexpr double kProbeWork = 1e9;
+    if (work > 0.0 && work < kProbeWork)
+        for (int i = 0; i < n_probe; ++i) {
+            const int full = grids[(int64_t)i * n_media / n_probe].nt;
+            pg[i].nt = (int)std::min<double>(full, std::ceil(pg[i].nt * kProbeWork / work));
+        }
     const size_t ts = dtype == FWI_F64 ? 8 : 4;
     hipStream_t st = nullptr;
     if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
