@@ -39,7 +39,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="uneven64", choices=["uneven64", "rodgauss512", "disc128", "ring188", "unfold16"])
     ap.add_argument("--unfold-k", type=int, default=8, help="unfolded iterations (unfold16)")
-    ap.add_argument("--unfold-backprop", default="fd", choices=["none", "fd"])
+    ap.add_argument("--unfold-backprop", default="exact", choices=["none", "fd", "exact"])
     ap.add_argument("--media", type=int, default=64, help="media of the uneven workload (ring188: phantoms, default 1)")
     ap.add_argument("--nt", type=int, default=0, help="override every medium's step count (counter runs)")
     ap.add_argument("--mode", default="batched", choices=["batched", "plain"])
@@ -180,7 +180,7 @@ def run_unfold(args):
     upd = sum(g.n_tx * g.nx * g.nz * g.nt * 2 for g in grids)
     times = []
     for it in range(args.warmup + args.steps):
-        c_in = c0.clone().requires_grad_(args.unfold_backprop == "fd")
+        c_in = c0.clone().requires_grad_(args.unfold_backprop != "none")
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         cK = model(c_in, rho, wav, d_obs)
@@ -196,7 +196,10 @@ def run_unfold(args):
     fw = float(np.mean([a for a, _ in times]))
     bw = float(np.mean([b for _, b in times]))
     grads_fw = args.unfold_k
-    grads_bw = 2 * args.unfold_k if args.unfold_backprop == "fd" else 0
+    # backward physics per unfolded iteration: two gradients (fd) or one
+    # Hessian-vector product (exact), counted here in gradient-equivalents
+    # of useful cell-updates (an HVP advances value and derivative together)
+    grads_bw = {"none": 0, "fd": 2, "exact": 1}[args.unfold_backprop] * args.unfold_k
     line = {
         "metric": "DUFWI unfolded forward+backward time", "value": round(fw + bw, 3), "unit": "s",
         "higher_is_better": False, "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,

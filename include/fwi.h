@@ -49,7 +49,7 @@ typedef enum fwi_status {
     FWI_ERR_NOMEM = 4,       /* the library could not allocate its plan-owned device tables     */
     FWI_ERR_WORKSPACE = 5,   /* workspace NULL or smaller than fwi_plan_workspace_size()        */
     FWI_ERR_HIP = 6,         /* a HIP runtime call failed (message in fwi_plan_last_error)      */
-    FWI_ERR_NONFINITE = 7,   /* non-finite traces or misfit were produced (found on the device) */
+    FWI_ERR_NONFINITE = 7,   /* non-finite traces, misfit or gradient (found on the device)     */
     FWI_ERR_MEDIUM = 8,      /* c <= 0, rho <= 0 or a non-finite c / rho (found on the device)  */
     FWI_ERR_STATE = 9        /* fwi_plan_adjoint without a preceding fwi_plan_forward            */
 } fwi_status;
@@ -122,6 +122,12 @@ typedef struct fwi_options {
                              /*    eq. 1-2; 4 = staggered fourth-order differences (one step per */
                              /*    launch, rows 1, 2 or 4, not persistent; stability bound with  */
                              /*    98/9 in place of 8)                                           */
+    int32_t hvp;             /* 1: the plan serves fwi_plan_hvp only (one step per launch, order */
+                             /*    2, not persistent, no graph, not forward_only; its workspace  */
+                             /*    holds value and derivative of every field)                    */
+    int32_t host_only;       /* 1: plan on the host only, with no HIP call (mem_budget > 0       */
+                             /*    required): sizes, info and fwi_plan_launches work, the calls  */
+                             /*    return FWI_ERR_INVALID                                        */
     int32_t reserved;
 } fwi_options;
 
@@ -143,7 +149,14 @@ typedef struct fwi_plan_info {
 
 /* Validate the geometry and options, copy the geometry, build the device
  * tables (damping profiles, per-tile receiver lists, work-item schedule).
- * Geometry errors are found on the host before any HIP call.
+ * Defines the discrete problem of Sec. II-A: one grid per medium, one source
+ * cell per transmit and a receiver subset per transmit, the damping profile
+ * D of eq. 1-2 with the quadratic layer of Sec. IV.  grids[n_media] is host
+ * memory read during the call only; *out receives a plan the caller frees
+ * with fwi_plan_destroy.  Geometry errors (FWI_ERR_GEOMETRY), option and size
+ * errors (FWI_ERR_INVALID) and the host stability check (FWI_ERR_CFL) are
+ * found on the host before any HIP call; fwi_last_create_error() holds the
+ * message and *out is NULL on failure.
  * Allocates plan-owned device memory (freed by fwi_plan_destroy). */
 fwi_status fwi_plan_create(fwi_plan **out, fwi_dtype dtype, const fwi_grid *grids,
                            int32_t n_media, const fwi_options *opt);
@@ -161,18 +174,83 @@ fwi_status fwi_plan_get_info(const fwi_plan *plan, fwi_plan_info *info);
 fwi_status fwi_plan_execute(fwi_plan *plan, const fwi_io *io, void *workspace,
                             size_t workspace_bytes, void *stream);
 
-/* Forward solve only: traces (and the misfit when d_obs is given).  Keeps
- * the replay state (checkpoints and the last segment) in the workspace for
- * a following fwi_plan_adjoint with the same c, rho and wavelet. */
+/* Forward solve only: the update of eq. 2 from zero initial fields with the
+ * source added at its cell each step, and the receiver samples of eq. 3
+ * (traces), plus the misfit of eq. 5 when d_obs is given.  Keeps the replay
+ * state (checkpoints and the last segment) in the workspace for a following
+ * fwi_plan_adjoint with the same c, rho and wavelet.  Arguments, ownership
+ * and errors as for fwi_plan_execute; the plan must hold one wave
+ * (FWI_ERR_INVALID otherwise). */
 fwi_status fwi_plan_forward(fwi_plan *plan, const fwi_io *io, void *workspace,
                             size_t workspace_bytes, void *stream);
 
 /* Adjoint and gradient from the state fwi_plan_forward left in the same
- * workspace.  The adjoint source is d_adj when given (it then plays the role
- * of dJ/dtraces), else 2 (traces - d_obs).  Writes grad_c / grad_rho.
- * The workspace state is consumed: a second adjoint needs a new forward. */
+ * workspace: the exact discrete adjoint of eq. 2 run backwards in time with
+ * the zero-lag imaging condition of eq. 6.  The adjoint source is d_adj when
+ * given (it then plays the role of dJ/dtraces, so the outputs are the
+ * vector-Jacobian product), else 2 (traces - d_obs).  Writes grad_c /
+ * grad_rho.  FWI_ERR_STATE when the workspace holds no forward state; the
+ * state is consumed: a second adjoint needs a new forward.  Other arguments,
+ * ownership and errors as for fwi_plan_execute. */
 fwi_status fwi_plan_adjoint(fwi_plan *plan, const fwi_io *io, void *workspace,
                             size_t workspace_bytes, void *stream);
+
+/* Direction and outputs of fwi_plan_hvp for one medium (device pointers in
+ * the plan's dtype, caller-owned, valid until the stream work completes). */
+typedef struct fwi_hvp_io {
+    const void *dc;          /* [nz][nx] direction, speed-of-sound component (m/s)              */
+    const void *drho;        /* [nz][nx] direction, density component, or NULL (= 0)            */
+    void *hv_c;              /* [nz][nx] out: speed-of-sound component of H v                   */
+    void *hv_rho;            /* [nz][nx] out: density component of H v, or NULL                 */
+    void *dtraces;           /* [n_tx][nt][n_rcv] out: tangent-linear traces (dF/dm) v, or NULL */
+} fwi_hvp_io;
+
+/* Hessian-vector product of the misfit J = sum (d - d_obs)^2 (eq. 5) of each
+ * medium in the direction v = (dc, drho): H v = d/de grad J(m + e v) at e = 0,
+ * the product that back-propagation through the unfolded gradient steps of
+ * eq. 9 needs (the Hessian is symmetric, so it is also the vector-Jacobian
+ * product of the gradient map of eq. 6).  Computed exactly (up to rounding)
+ * by forward-mode differentiation of the gradient: the forward solve carries
+ * the tangent-linear fields, the adjoint the second-order adjoint fields
+ * (driven by twice the tangent-linear traces), and the imaging condition
+ * their derivative.  The plan must have been created with options.hvp = 1
+ * (FWI_ERR_INVALID otherwise).  io as for fwi_plan_execute with d_obs
+ * required: it also receives the traces, the misfit and (when grad_c /
+ * grad_rho are given) the gradient at m.  dir[n_media] as declared above;
+ * dc and hv_c are required.  Asynchronous on ``stream``; device-side
+ * failures (a bad medium or direction, non-finite results) are reported by
+ * fwi_plan_check(). */
+fwi_status fwi_plan_hvp(fwi_plan *plan, const fwi_io *io, const fwi_hvp_io *dir, void *workspace,
+                        size_t workspace_bytes, void *stream);
+
+/* One kernel launch of a call's sequence, as fwi_plan_launches lists it. */
+typedef enum fwi_kernel {
+    FWI_K_FWD1 = 0, FWI_K_FWD2 = 1, FWI_K_ADJ1 = 2, FWI_K_ADJ2 = 3, FWI_K_FWD3 = 4,
+    FWI_K_FWD4 = 5, FWI_K_ADJ4 = 6,          /* fourth-order operator, one step */
+    FWI_K_PERSISTENT = 7, FWI_K_FILL = 8, FWI_K_PREP = 9, FWI_K_MISFIT_PARTIAL = 10,
+    FWI_K_MISFIT_FINAL = 11, FWI_K_FINALIZE = 12,
+    FWI_K_PREP_HVP = 13, FWI_K_PACK_HVP = 14, FWI_K_UNPACK_HVP = 15, FWI_K_FINALIZE_HVP = 16
+} fwi_kernel;
+
+typedef struct fwi_launch {
+    int32_t kernel;          /* fwi_kernel                                                      */
+    int32_t wave;            /* wave of the step loop, -1 outside it                            */
+    int32_t step;            /* launch index within the wave's schedule, -1 outside the loop    */
+    int32_t grid_x, grid_y;  /* workgroups (grid_x * grid_y in all)                             */
+    int32_t block;           /* work-items per workgroup                                        */
+    int32_t lds_bytes;       /* dynamic LDS per workgroup                                       */
+    int32_t reserved;
+} fwi_launch;
+
+/* The launch sequence of one call, computed on the host by the same code
+ * that enqueues it (no HIP call): call 0 = fwi_plan_execute with gradients,
+ * 1 = fwi_plan_forward, 2 = fwi_plan_adjoint, 3 = fwi_plan_hvp.  Writes the
+ * first min(capacity, count) launches to out (host memory, may be NULL when
+ * capacity is 0) and the total to *count.  The persistent kernel's grid is
+ * 0 on a host-only plan (it depends on the device's occupancy).
+ * FWI_ERR_INVALID for a call the plan cannot serve. */
+fwi_status fwi_plan_launches(const fwi_plan *plan, int32_t call, fwi_launch *out, int64_t capacity,
+                             int64_t *count);
 
 /* Wait for the plan's last queued call and report device-side failures
  * (FWI_ERR_CFL, FWI_ERR_MEDIUM, FWI_ERR_NONFINITE) or FWI_OK. */

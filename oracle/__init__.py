@@ -7,7 +7,8 @@ seeded inputs of ``workloads``.
 
 ``run`` wraps the plain C implementation in ``fwi_oracle.c`` (forward solve,
 misfit, exact discrete adjoint and zero-lag imaging, Sec. II-A eq. 1-6);
-``born`` is the test-only tangent-linear model; ``green2d_trace`` is the
+``born`` is the test-only tangent-linear model; ``hvp`` the Hessian-vector
+product of the misfit (differences of gradients); ``green2d_trace`` is the
 analytic homogeneous 2-D Green's-function response used to pin the forward
 solver's scaling and timing.
 """
@@ -185,6 +186,40 @@ def born(geom, c, rho, wavelet, dc, drho) -> np.ndarray:
     if rc != 0:
         raise RuntimeError(f"oracle om_born failed with status {rc}")
     return out
+
+
+def hvp(geom, c, rho, wavelet, d_obs, dc, drho, rel_step: float = 1e-4, ckpt: int = 0,
+        threads: int = 0) -> dict:
+    """Hessian-vector product of the misfit J = sum (d - d_obs)^2 (eq. 5) in
+    the direction v = (dc, drho): the directional derivative of the gradient
+    of eq. 6, d/de grad J(c + e dc, rho + e drho) at e = 0 (the quantity
+    that back-propagation through an unfolded gradient step, eq. 9, needs).
+
+    Central differences of the oracle gradient with one Richardson
+    extrapolation (truncation error O(e^4)):
+        D(e) = (g(m + e v) - g(m - e v)) / (2 e),   Hv = (4 D(e/2) - D(e)) / 3,
+    the step e chosen so that the largest relative change of any cell's c or
+    rho is ``rel_step``.  Returns ``hv_c``, ``hv_rho`` [nz, nx] (the c and rho
+    components of H v) and the step used."""
+    c = _f64(c); rho = _f64(rho); dc = _f64(dc); drho = _f64(drho)
+    scale = max(float(np.max(np.abs(dc) / np.abs(c))), float(np.max(np.abs(drho) / np.abs(rho))))
+    if scale == 0.0:
+        z = np.zeros((geom.nz, geom.nx))
+        return {"hv_c": z, "hv_rho": z.copy(), "step": 0.0}
+    e = rel_step / scale
+
+    def grad(sign, step):
+        r = run(geom, c + sign * step * dc, rho + sign * step * drho, wavelet, d_obs=d_obs, ckpt=ckpt,
+                threads=threads)
+        return r["grad_c"], r["grad_rho"]
+
+    def central(step):
+        (pc, pr), (mc, mr) = grad(1.0, step), grad(-1.0, step)
+        return (pc - mc) / (2 * step), (pr - mr) / (2 * step)
+
+    c1, r1 = central(e)
+    c2, r2 = central(e / 2)
+    return {"hv_c": (4 * c2 - c1) / 3, "hv_rho": (4 * r2 - r1) / 3, "step": e}
 
 
 def green2d_trace(wavelet_fn, r: float, c: float, h: float, dt: float, nt: int,

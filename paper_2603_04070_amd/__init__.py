@@ -19,7 +19,7 @@ import numpy as np
 
 from . import _abi
 
-__all__ = ["GridSpec", "FwiError", "Plan", "gradient", "forward", "autotune"]
+__all__ = ["GridSpec", "FwiError", "Plan", "gradient", "forward", "autotune", "hessian_vector"]
 
 
 class FwiError(RuntimeError):
@@ -90,13 +90,17 @@ class Plan:
     ``steps_per_launch``: forward-type steps fused per launch (0 =
     automatic: 3 batched, 1 plain; adjoint launches fuse at most 2).
     ``order``: 2 (the 5-point flux form) or 4 (staggered fourth-order
-    differences, one step per launch).
+    differences, one step per launch).  ``hvp``: the plan serves
+    ``hessian_vector`` (fwi_plan_hvp) only.  ``host_only``: plan on the host
+    without any HIP call (needs ``mem_budget``): sizes, ``info`` and
+    ``launches`` only.
     """
 
     def __init__(self, grids: Sequence[GridSpec], dtype: str = "f32", mode: str = "batched",
                  ckpt: int = 0, group: int = 0, rows: int = 0, use_graph: bool = False,
                  acc_double: bool = False, mem_budget: float = 0.0, steps_per_launch: int = 0,
-                 forward_only: bool = False, persistent: bool = False, barrier_spin: int = 0, order: int = 2):
+                 forward_only: bool = False, persistent: bool = False, barrier_spin: int = 0, order: int = 2,
+                 hvp: bool = False, host_only: bool = False):
         lib = _lib()
         self.grids = list(grids)
         self.dtype = dtype
@@ -123,7 +127,10 @@ class Plan:
         opt.barrier_spin = int(barrier_spin)
         opt.mem_budget = float(mem_budget)
         opt.order = int(order)
+        opt.hvp = int(bool(hvp))
+        opt.host_only = int(bool(host_only))
         self.order = int(order)
+        self.hvp_plan = bool(hvp)
         self._h = C.c_void_p()
         dt = _abi.FWI_F64 if dtype == "f64" else _abi.FWI_F32
         st = lib.fwi_plan_create(C.byref(self._h), dt, arr, len(self.grids), C.byref(opt))
@@ -144,6 +151,22 @@ class Plan:
         inf = _abi.FwiPlanInfo()
         _lib().fwi_plan_get_info(self._h, C.byref(inf))
         return {k: getattr(inf, k) for k, _ in _abi.FwiPlanInfo._fields_}
+
+    def launches(self, call: str = "execute") -> list:
+        """The kernel launches one call enqueues (fwi_plan_launches), as dicts
+        with kernel name, wave, step, grid, block and dynamic LDS bytes."""
+        lib = _lib()
+        code = {"execute": 0, "forward": 1, "adjoint": 2, "hvp": 3}[call]
+        n = C.c_int64()
+        st = lib.fwi_plan_launches(self._h, code, None, 0, C.byref(n))
+        if st != _abi.FWI_OK:
+            self._raise(st)
+        arr = (_abi.FwiLaunch * max(1, n.value))()
+        st = lib.fwi_plan_launches(self._h, code, arr, n.value, C.byref(n))
+        if st != _abi.FWI_OK:
+            self._raise(st)
+        return [{"kernel": _abi.KERNEL_NAMES[a.kernel], "wave": a.wave, "step": a.step,
+                 "grid": (a.grid_x, a.grid_y), "block": a.block, "lds_bytes": a.lds_bytes} for a in arr[:n.value]]
 
     def _raise(self, st):
         raise FwiError(st, _lib().fwi_plan_last_error(self._h).decode())
@@ -169,6 +192,20 @@ class Plan:
     def execute(self, ios, workspace, stream=None):
         """Forward, misfit, adjoint and gradient of every medium (asynchronous)."""
         self._call(_lib().fwi_plan_execute, ios, workspace, stream)
+
+    def hvp(self, ios, dirs, workspace, stream=None):
+        """Hessian-vector products (fwi_plan_hvp): ``dirs[i]`` holds ``dc``,
+        optionally ``drho``, and the outputs ``hv_c``, optionally ``hv_rho`` and
+        ``dtraces``."""
+        arr = self._ios(ios)
+        d = (_abi.FwiHvpIO * len(self.grids))()
+        for i, x in enumerate(dirs):
+            d[i] = _abi.FwiHvpIO(_ptr(x["dc"]), _ptr(x.get("drho")), _ptr(x["hv_c"]), _ptr(x.get("hv_rho")),
+                                 _ptr(x.get("dtraces")))
+        st = _lib().fwi_plan_hvp(self._h, arr, d, C.c_void_p(workspace.data_ptr()),
+                                 C.c_size_t(workspace.numel() * workspace.element_size()), _stream_handle(stream))
+        if st != _abi.FWI_OK:
+            self._raise(st)
 
     def forward(self, ios, workspace, stream=None):
         self._call(_lib().fwi_plan_forward, ios, workspace, stream)
@@ -250,6 +287,43 @@ def gradient(plan: Plan, media: List[dict], workspace=None, stream=None, want_gr
     if workspace is None:
         workspace = plan.new_workspace(dev)
     plan.execute(ios, workspace, stream)
+    if check:
+        plan.check()
+    return outs
+
+
+def hessian_vector(plan: Plan, media: List[dict], dirs: List[dict], workspace=None, stream=None,
+                   check: bool = True, want_dtraces: bool = False) -> List[dict]:
+    """Hessian-vector product of each medium's misfit ||F(c, rho) - d_obs||^2
+    in the direction (dc, drho) on an ``hvp`` plan.  ``media[i]`` holds ``c``,
+    ``rho``, ``wavelet``, ``d_obs``; ``dirs[i]`` holds ``dc`` and optionally
+    ``drho``.  Returns per medium ``hv_c``, ``hv_rho``, ``traces``, ``misfit``,
+    ``grad_c``, ``grad_rho`` (the gradient at (c, rho)) and, when asked,
+    ``dtraces`` (the tangent-linear traces)."""
+    import torch
+    if not plan.hvp_plan:
+        raise ValueError("hessian_vector needs a Plan(..., hvp=True)")
+    td = _torch_dtype(plan.dtype)
+    dev = media[0]["c"].device
+    ios, ds, outs = [], [], []
+    for g, m, v in zip(plan.grids, media, dirs):
+        o = {"traces": torch.empty((g.n_tx, g.nt, g.n_rcv), dtype=td, device=dev),
+             "misfit": torch.zeros(1, dtype=torch.float64, device=dev),
+             "grad_c": torch.empty((g.nz, g.nx), dtype=td, device=dev),
+             "grad_rho": torch.empty((g.nz, g.nx), dtype=td, device=dev),
+             "hv_c": torch.empty((g.nz, g.nx), dtype=td, device=dev),
+             "hv_rho": torch.empty((g.nz, g.nx), dtype=td, device=dev)}
+        if want_dtraces:
+            o["dtraces"] = torch.empty((g.n_tx, g.nt, g.n_rcv), dtype=td, device=dev)
+        io = dict(m)
+        io.update({k: o[k] for k in ("traces", "misfit", "grad_c", "grad_rho")})
+        ios.append(io)
+        ds.append({"dc": v["dc"].contiguous(), "drho": None if v.get("drho") is None else v["drho"].contiguous(),
+                   "hv_c": o["hv_c"], "hv_rho": o["hv_rho"], "dtraces": o.get("dtraces")})
+        outs.append(o)
+    if workspace is None:
+        workspace = plan.new_workspace(dev)
+    plan.hvp(ios, ds, workspace, stream)
     if check:
         plan.check()
     return outs

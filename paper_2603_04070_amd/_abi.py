@@ -18,6 +18,7 @@ EXPORTS = (
     "fwi_plan_create", "fwi_plan_workspace_size", "fwi_plan_get_info", "fwi_plan_execute",
     "fwi_plan_forward", "fwi_plan_adjoint", "fwi_plan_check", "fwi_plan_destroy",
     "fwi_status_string", "fwi_plan_last_error", "fwi_last_create_error", "fwi_autotune",
+    "fwi_plan_hvp", "fwi_plan_launches",
 )
 
 
@@ -48,7 +49,28 @@ class FwiOptions(C.Structure):
         ("persistent", C.c_int32), ("barrier_spin", C.c_int32),
         ("mem_budget", C.c_double),
         ("tune_cache", C.c_char_p),
-        ("order", C.c_int32), ("reserved", C.c_int32),
+        ("order", C.c_int32), ("hvp", C.c_int32),
+        ("host_only", C.c_int32), ("reserved", C.c_int32),
+    ]
+
+
+class FwiLaunch(C.Structure):
+    _fields_ = [
+        ("kernel", C.c_int32), ("wave", C.c_int32), ("step", C.c_int32),
+        ("grid_x", C.c_int32), ("grid_y", C.c_int32), ("block", C.c_int32),
+        ("lds_bytes", C.c_int32), ("reserved", C.c_int32),
+    ]
+
+
+KERNEL_NAMES = ("fwd1", "fwd2", "adj1", "adj2", "fwd3", "fwd4", "adj4", "persistent", "fill", "prep",
+                "misfit_partial", "misfit_final", "finalize", "prep_hvp", "pack_hvp", "unpack_hvp",
+                "finalize_hvp")
+
+
+class FwiHvpIO(C.Structure):
+    _fields_ = [
+        ("dc", C.c_void_p), ("drho", C.c_void_p), ("hv_c", C.c_void_p), ("hv_rho", C.c_void_p),
+        ("dtraces", C.c_void_p),
     ]
 
 
@@ -87,6 +109,10 @@ def load():
     lib.fwi_plan_get_info.argtypes = [P, C.POINTER(FwiPlanInfo)]
     for name in ("fwi_plan_execute", "fwi_plan_forward", "fwi_plan_adjoint"):
         getattr(lib, name).argtypes = [P, C.POINTER(FwiIO), P, C.c_size_t, P]
+    lib.fwi_plan_launches.argtypes = [P, C.c_int32, C.POINTER(FwiLaunch), C.c_int64, C.POINTER(C.c_int64)]
+    lib.fwi_plan_launches.restype = C.c_int
+    lib.fwi_plan_hvp.argtypes = [P, C.POINTER(FwiIO), C.POINTER(FwiHvpIO), P, C.c_size_t, P]
+    lib.fwi_plan_hvp.restype = C.c_int
     lib.fwi_plan_check.argtypes = [P]
     lib.fwi_plan_destroy.argtypes = [P]
     lib.fwi_plan_destroy.restype = None

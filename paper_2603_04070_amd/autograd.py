@@ -35,6 +35,9 @@ class _Forward(torch.autograd.Function):
             outs.append(tr)
         ws = plan.new_workspace(dev)
         plan.forward(ios, ws)
+        # device-side failures (a bad medium, c above c_max, non-finite
+        # traces) surface here rather than as silent values
+        plan.check()
         ctx.plan = plan
         ctx.ws = ws
         ctx.ios = ios

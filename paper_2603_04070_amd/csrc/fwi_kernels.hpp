@@ -88,6 +88,85 @@ struct alignas(sizeof(T) * G) Vec {
     T v[G];
 };
 
+// ---------------------------------------------------------------- dual numbers
+//
+// A value and its derivative along one direction of the medium, (x, x').
+// Instantiating the one-step kernels on Dual<S> differentiates the whole
+// gradient computation forward along that direction: the forward fields
+// carry their tangent-linear perturbation, the adjoint fields the
+// second-order adjoint (its source 2 d' comes from the traces' tangents),
+// and the imaging sums their derivatives -- so the gradient's tangent is
+// the Hessian-vector product of the misfit, exact up to rounding.  Every
+// operation below is the product or quotient rule written with explicit
+// fused multiply-adds and contraction off, so a kernel rounds the same way
+// on every pass (checkpointed replay stays bitwise).
+template <typename S>
+struct Dual {
+    S v, d;
+    __host__ __device__ constexpr Dual() : v(S(0)), d(S(0)) {}
+    __host__ __device__ constexpr Dual(double x) : v(S(x)), d(S(0)) {}
+    __host__ __device__ constexpr Dual(S x, S dx) : v(x), d(dx) {}
+    template <typename R>
+    __host__ __device__ explicit constexpr Dual(const Dual<R>& o) : v(S(o.v)), d(S(o.d)) {}
+    __host__ __device__ explicit operator double() const { return (double)v; }
+};
+
+template <typename T>
+struct DualOf { static constexpr bool is = false; using scalar = T; };
+template <typename S>
+struct DualOf<Dual<S>> { static constexpr bool is = true; using scalar = S; };
+
+template <typename S>
+__host__ __device__ __forceinline__ Dual<S> operator+(Dual<S> a, Dual<S> b)
+{
+#pragma clang fp contract(off)
+    return Dual<S>(a.v + b.v, a.d + b.d);
+}
+template <typename S>
+__host__ __device__ __forceinline__ Dual<S> operator-(Dual<S> a, Dual<S> b)
+{
+#pragma clang fp contract(off)
+    return Dual<S>(a.v - b.v, a.d - b.d);
+}
+template <typename S>
+__host__ __device__ __forceinline__ Dual<S> operator-(Dual<S> a)
+{
+    return Dual<S>(-a.v, -a.d);
+}
+template <typename S>
+__host__ __device__ __forceinline__ Dual<S> operator*(Dual<S> a, Dual<S> b)
+{
+#pragma clang fp contract(off)
+    return Dual<S>(a.v * b.v, fma(a.d, b.v, a.v * b.d));
+}
+template <typename S>
+__host__ __device__ __forceinline__ Dual<S> operator/(Dual<S> a, Dual<S> b)
+{
+#pragma clang fp contract(off)
+    const S q = a.v / b.v;
+    return Dual<S>(q, (a.d - q * b.d) / b.v);
+}
+// the scalar overloads stay visible next to the dual one
+using ::fma;
+
+template <typename S>
+__host__ __device__ __forceinline__ Dual<S> fma(Dual<S> a, Dual<S> b, Dual<S> c)
+{
+#pragma clang fp contract(off)
+    return Dual<S>(fma(a.v, b.v, c.v), fma(a.d, b.v, fma(a.v, b.d, c.d)));
+}
+template <typename S>
+__host__ __device__ __forceinline__ Dual<S>& operator+=(Dual<S>& a, Dual<S> b)
+{
+    a = a + b;
+    return a;
+}
+template <typename S>
+__host__ __device__ __forceinline__ bool operator==(Dual<S> a, Dual<S> b)
+{
+    return a.v == b.v;
+}
+
 // Every buffer the kernels touch outside LDS is device global memory.  The
 // pointers reach the kernels inside work-item descriptors, where the compiler
 // cannot see their address space; without the cast it emits flat loads, which
@@ -96,13 +175,30 @@ struct alignas(sizeof(T) * G) Vec {
 template <typename T>
 __device__ __forceinline__ T ldg(const T* p, int64_t i)
 {
-    return ((const T __attribute__((address_space(1)))*)p)[i];
+    if constexpr (DualOf<T>::is) {
+        // one access for the (value, derivative) pair
+        using S = typename DualOf<T>::scalar;
+        typedef S P2 __attribute__((ext_vector_type(2)));
+        const P2 v = ((const P2 __attribute__((address_space(1)))*)p)[i];
+        return T(v[0], v[1]);
+    } else {
+        return ((const T __attribute__((address_space(1)))*)p)[i];
+    }
 }
 
 template <typename T>
 __device__ __forceinline__ void stg(T* p, int64_t i, T v)
 {
-    ((T __attribute__((address_space(1)))*)p)[i] = v;
+    if constexpr (DualOf<T>::is) {
+        using S = typename DualOf<T>::scalar;
+        typedef S P2 __attribute__((ext_vector_type(2)));
+        P2 w;
+        w[0] = v.v;
+        w[1] = v.d;
+        ((P2 __attribute__((address_space(1)))*)p)[i] = w;
+    } else {
+        ((T __attribute__((address_space(1)))*)p)[i] = v;
+    }
 }
 
 // The G values of a cell move as one native vector (one 16-byte access for
@@ -119,6 +215,13 @@ struct Native<T, 1> {
 template <typename T, int G>
 __device__ __forceinline__ Vec<T, G> vload(const T* p, int64_t cell)
 {
+    if constexpr (DualOf<T>::is) {
+        // dual fields: G consecutive (value, tangent) pairs
+        Vec<T, G> r;
+#pragma unroll
+        for (int g = 0; g < G; ++g) r.v[g] = ldg(p, cell * G + g);
+        return r;
+    } else {
     using N = typename Native<T, G>::type;
     const N n = *(const N __attribute__((address_space(1)))*)(p + cell * G);
     Vec<T, G> r;
@@ -129,11 +232,16 @@ __device__ __forceinline__ Vec<T, G> vload(const T* p, int64_t cell)
         for (int g = 0; g < G; ++g) r.v[g] = n[g];
     }
     return r;
+    }
 }
 
 template <typename T, int G>
 __device__ __forceinline__ void vstore(T* p, int64_t cell, const Vec<T, G>& v)
 {
+    if constexpr (DualOf<T>::is) {
+#pragma unroll
+        for (int g = 0; g < G; ++g) stg(p, cell * G + g, v.v[g]);
+    } else {
     using N = typename Native<T, G>::type;
     N n;
     if constexpr (G == 1) {
@@ -143,6 +251,7 @@ __device__ __forceinline__ void vstore(T* p, int64_t cell, const Vec<T, G>& v)
         for (int g = 0; g < G; ++g) n[g] = v.v[g];
     }
     *(N __attribute__((address_space(1)))*)(p + cell * G) = n;
+    }
 }
 
 // The same accesses with a 32-bit element index into a plane whose base is
@@ -1904,7 +2013,9 @@ __global__ void fill_kernel(T* __restrict__ p, int64_t n, T v)
         p[i] = v;
 }
 
-// Misfit partial sums: block b of medium m sums (d - d_obs)^2 over a strided share.
+// Misfit partial sums: block b of medium m sums (d - d_obs)^2 over a strided
+// share.  Without observed traces it sums (0 d)^2, which is zero unless a
+// trace sample is not finite, so that every forward solve checks its traces.
 constexpr int kMisfitBlocks = 64;
 
 template <typename T>
@@ -1912,23 +2023,20 @@ __global__ __launch_bounds__(256) void misfit_partial_kernel(const MediumDev<T>*
                                                               double* __restrict__ partial)
 {
     const MediumDev<T>& m = media[blockIdx.y];
-    __shared__ double red[256];
+    __shared__ double red[4];
     double s = 0.0;
-    if (m.d_obs) {
-        const int64_t n = (int64_t)m.n_tx * m.nt * m.n_rcv;
-        for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-             i += (int64_t)gridDim.x * blockDim.x) {
-            const double r = (double)m.traces[i] - (double)m.d_obs[i];
-            s += r * r;
-        }
+    const int64_t n = (int64_t)m.n_tx * m.nt * m.n_rcv;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const double d = (double)m.traces[i];
+        const double r = m.d_obs ? d - (double)m.d_obs[i] : 0.0 * d;
+        s += r * r;
     }
-    red[threadIdx.x] = s;
+    // wavefront reduction by lane shuffles, then the four wave sums in a fixed order
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
     __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) partial[blockIdx.y * kMisfitBlocks + blockIdx.x] = red[0];
+    if (threadIdx.x == 0) partial[blockIdx.y * kMisfitBlocks + blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
 template <typename T>
@@ -1975,6 +2083,127 @@ __global__ void finalize_kernel(const MediumDev<T>* __restrict__ media, unsigned
         if (!isfinite(gc) || !isfinite(gr)) flag |= kFlagNonfinite;
         if (m.grad_c) m.grad_c[x] = (T)gc;
         if (m.grad_rho) m.grad_rho[x] = (T)gr;
+    }
+    if (flag) atomicOr(status, flag);
+}
+
+// ---------------------------------------------------------------- Hessian-vector product
+//
+// Host-facing arrays stay plain; the dual copies live in the workspace.  One
+// descriptor per medium.
+template <typename S>
+struct MediumHvp {
+    int32_t nx, nz, n_tx, nt;
+    int32_t n_rcv, npml, acc_slots, wavelet_shared;
+    double h, dt, dmax, c_max;
+    int64_t acc_stride;               // elements between two accumulator slots
+    const S* c;
+    const S* rho;
+    const S* dc;                      // direction (c component)
+    const S* drho;                    // direction (rho component), or NULL = 0
+    const S* wavelet;
+    const S* d_obs;
+    S* traces;                        // out: primal traces
+    S* dtraces;                       // out: tangent-linear traces, or NULL
+    S* grad_c;
+    S* grad_rho;
+    S* hv_c;
+    S* hv_rho;
+    Dual<S>* coef;                    // [nz*nx] x (Q, bt) with their derivatives
+    Dual<S>* wav;                     // dual wavelet rows
+    Dual<S>* obs;                     // dual observed traces (zero derivative)
+    Dual<S>* tr;                      // dual traces written by the forward kernels
+    const void* acc0;                 // dual accumulators of the medium's first slot
+};
+
+// (Q, bt) and their derivatives along (dc, drho), in double and rounded once:
+// Q = gamma rho c^2 / (h^2 rho_ref), dQ = gamma (drho c^2 + 2 rho c dc) / (h^2 rho_ref),
+// bt = rho_ref / rho, dbt = -rho_ref drho / rho^2.
+template <typename S>
+__global__ void prep_hvp_kernel(const MediumHvp<S>* __restrict__ media, unsigned* status)
+{
+    const MediumHvp<S>& m = media[blockIdx.y];
+    const int64_t n = (int64_t)m.nx * m.nz;
+    const double ih2 = 1.0 / (m.h * m.h);
+    unsigned flag = 0;
+    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n;
+         x += (int64_t)gridDim.x * blockDim.x) {
+        const int ix = (int)(x % m.nx), iz = (int)(x / m.nx);
+        const double c = (double)m.c[x], rho = (double)m.rho[x];
+        const double dc = (double)m.dc[x], drho = m.drho ? (double)m.drho[x] : 0.0;
+        if (!(c > 0.0) || !(rho > 0.0) || !isfinite(c) || !isfinite(rho)) flag |= kFlagMedium;
+        if (!isfinite(dc) || !isfinite(drho)) flag |= kFlagMedium;
+        if (c > m.c_max) flag |= kFlagCfl;
+        const double e = (dprof(ix, m.nx, m.npml, m.dmax) + dprof(iz, m.nz, m.npml, m.dmax)) * m.dt;
+        const double k = m.dt * m.dt / (1.0 + e) * ih2 / kRhoRef;
+        m.coef[2 * x] = Dual<S>((S)(k * rho * c * c), (S)(k * (drho * c * c + 2.0 * rho * c * dc)));
+        m.coef[2 * x + 1] = Dual<S>((S)(kRhoRef / rho), (S)(-kRhoRef * drho / (rho * rho)));
+    }
+    if (flag) atomicOr(status, flag);
+}
+
+// Dual copies of the wavelet and the observed traces (both independent of the medium).
+template <typename S>
+__global__ void pack_hvp_kernel(const MediumHvp<S>* __restrict__ media)
+{
+    const MediumHvp<S>& m = media[blockIdx.y];
+    const int64_t nw = (int64_t)(m.wavelet_shared ? 1 : m.n_tx) * m.nt;
+    const int64_t no = (int64_t)m.n_tx * m.nt * m.n_rcv;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nw + no;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        if (i < nw) m.wav[i] = Dual<S>(m.wavelet[i], S(0));
+        else m.obs[i - nw] = Dual<S>(m.d_obs[i - nw], S(0));
+    }
+}
+
+// Primal traces and their tangent-linear part out of the dual traces.
+template <typename S>
+__global__ void unpack_hvp_kernel(const MediumHvp<S>* __restrict__ media)
+{
+    const MediumHvp<S>& m = media[blockIdx.y];
+    const int64_t n = (int64_t)m.n_tx * m.nt * m.n_rcv;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const Dual<S> d = m.tr[i];
+        m.traces[i] = d.v;
+        if (m.dtraces) m.dtraces[i] = d.d;
+    }
+}
+
+// The gradient of finalize_kernel evaluated in dual double arithmetic with
+// c and rho carrying the direction: values = g_c, g_rho; derivatives = the
+// c and rho components of H v.
+template <typename S, typename A>
+__global__ void finalize_hvp_kernel(const MediumHvp<S>* __restrict__ media, unsigned* status)
+{
+    using D = Dual<double>;
+    const MediumHvp<S>& m = media[blockIdx.y];
+    const int64_t n = (int64_t)m.nx * m.nz;
+    const Dual<A>* acc = reinterpret_cast<const Dual<A>*>(m.acc0);
+    unsigned flag = 0;
+    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n;
+         x += (int64_t)gridDim.x * blockDim.x) {
+        D sk(0.0), sb(0.0);
+        for (int k = 0; k < m.acc_slots; ++k) {
+            sk += D(acc[k * m.acc_stride + x]);
+            sb += D(acc[k * m.acc_stride + n + x]);
+        }
+        const int ix = (int)(x % m.nx), iz = (int)(x / m.nx);
+        const double e = (dprof(ix, m.nx, m.npml, m.dmax) + dprof(iz, m.nz, m.npml, m.dmax)) * m.dt;
+        const double gam = m.dt * m.dt / (1.0 + e);
+        // the accumulated kappa sum is q times the lambda one (the kernels carry w = q lam)
+        const D s = sk / D(m.coef[2 * x]);
+        const D gk = D(gam / (m.h * m.h * kRhoRef)) * s;
+        const D gb = D(-kRhoRef) * sb;
+        const D c((double)m.c[x], (double)m.dc[x]);
+        const D rho((double)m.rho[x], m.drho ? (double)m.drho[x] : 0.0);
+        const D gc = D(2.0) * rho * c * gk;
+        const D gr = c * c * gk - gb / (rho * rho);
+        if (!isfinite(gc.v) || !isfinite(gr.v) || !isfinite(gc.d) || !isfinite(gr.d)) flag |= kFlagNonfinite;
+        if (m.grad_c) m.grad_c[x] = (S)gc.v;
+        if (m.grad_rho) m.grad_rho[x] = (S)gr.v;
+        m.hv_c[x] = (S)gc.d;
+        if (m.hv_rho) m.hv_rho[x] = (S)gr.d;
     }
     if (flag) atomicOr(status, flag);
 }

@@ -57,6 +57,7 @@ struct MediumPlan {
     int item0, item1;
     int acc_slots;
     size_t coef_off, acc_off;  // workspace
+    size_t wav_off, obs_off, trd_off;   // workspace, hvp plans: dual wavelet, observed and traces
     size_t ex_off, ez_off;     // plan tables
 };
 
@@ -68,6 +69,7 @@ struct fwi_plan {
     int G = 1, rows = 4, S = 1, nlam = 2, order = 2;
     int Sa = 1;                     // adjoint steps per launch (S: forward-type steps)
     bool acc_double = false;
+    bool hvp = false;               // dual-number plan of fwi_plan_hvp
     size_t tsize = 4, asize = 4;
     std::vector<MediumPlan> media;
     std::vector<ItemPlan> items;
@@ -89,6 +91,8 @@ struct fwi_plan {
     int2* d_blocks = nullptr;
     void* d_items = nullptr;        // Item<T, Acc>[n_items]
     void* d_media = nullptr;        // MediumDev<T>[n_media]
+    void* d_hvp = nullptr;          // MediumHvp<T>[n_media] (hvp plans)
+    size_t hvp_bytes = 0;
     unsigned* d_status = nullptr;
     unsigned* d_bar = nullptr;      // grid barrier words of the persistent form
     int pgrid = 0;                  // co-resident workgroups of the persistent kernel
@@ -138,6 +142,22 @@ double prof(int i, int n, int N, double dmax)
     if (i < N) { double r = (double)(N - i) / N; return dmax * r * r; }
     if (i > n - 1 - N) { double r = (double)(i - (n - 1 - N)) / N; return dmax * r * r; }
     return 0.0;
+}
+
+// Launch recorder of fwi_plan_launches: while ``out`` is set, the enqueue
+// functions append what they would launch instead of launching it.
+struct LaunchRec {
+    std::vector<fwi_launch>* out = nullptr;
+    int wave = -1, step = -1;
+};
+thread_local LaunchRec g_rec;
+
+bool recording() { return g_rec.out != nullptr; }
+
+void record(int kernel, dim3 grid, dim3 block, size_t lds)
+{
+    g_rec.out->push_back(fwi_launch{kernel, g_rec.wave, g_rec.step, (int32_t)grid.x, (int32_t)grid.y,
+                                    (int32_t)(block.x * block.y * block.z), (int32_t)lds, 0});
 }
 
 // Host-side validation of one grid (no HIP call).
@@ -284,8 +304,41 @@ void launch_step_g(int G, int kind, dim3 grid, hipStream_t st, const void* items
     else launch_step<T, Acc, 4>(kind, grid, st, items, blocks, s, mode, rows, order);
 }
 
+// Dynamic LDS of a step launch of this plan (compile-time tile layouts).
+template <typename T, int G>
+size_t lds_of(int kind, int rows, int order)
+{
+    auto byR = [&](auto r) -> size_t {
+        constexpr int R = decltype(r)::value;
+        if (order == 4) return kind == 0 ? Lds4<T, G, R, false>::bytes : Lds4<T, G, R, true>::bytes;
+        if (kind == 1) return Lds2<T, G, R, false>::bytes;
+        if (kind == 3) return Lds2<T, G, R, true>::bytes;
+        return Lds3<T, G, R>::bytes;
+    };
+    if (order != 4 && (kind == 0 || kind == 2)) return 0;
+    if (rows == 1) return byR(std::integral_constant<int, 1>());
+    if (rows == 2) return byR(std::integral_constant<int, 2>());
+    return byR(std::integral_constant<int, 4>());
+}
+
+size_t step_lds(const fwi_plan* p, int kind)
+{
+    auto byG = [&](auto t) -> size_t {
+        using T = decltype(t);
+        if (p->G == 1) return lds_of<T, 1>(kind, p->rows, p->order);
+        if (p->G == 2) return lds_of<T, 2>(kind, p->rows, p->order);
+        return lds_of<T, 4>(kind, p->rows, p->order);
+    };
+    return p->dtype == FWI_F64 ? byG(double()) : byG(float());
+}
+
 void step(fwi_plan* p, int kind, dim3 grid, hipStream_t st, const int2* blocks, int s, int mode)
 {
+    if (recording()) {
+        const int id = p->order == 4 ? (kind == 0 ? FWI_K_FWD4 : FWI_K_ADJ4) : kind;
+        record(id, grid, dim3(kTileX, kWavesZ), step_lds(p, kind));
+        return;
+    }
     if (p->dtype == FWI_F64)
         launch_step_g<double, double>(p->G, kind, grid, st, p->d_items, blocks, s, mode, p->rows, p->order);
     else if (p->acc_double)
@@ -376,6 +429,7 @@ void launch_persistent(fwi_plan* p, hipStream_t st, const Wave& w, int mode_idx,
     unsigned* bar = p->d_bar;
     unsigned spin = p->spin_limit;
     unsigned* status = p->d_status;
+    if (recording()) { record(FWI_K_PERSISTENT, dim3(p->pgrid > 0 ? grid : 0), dim3(kTileX, kWavesZ), lds); return; }
     void* args[] = {&items, &blocks, &nblk, &n_launch, &mode, &rows, &bar, &spin, &status};
     (void)hipLaunchKernel(fn, dim3(grid), dim3(kTileX, kWavesZ), args, lds, st);
 }
@@ -410,8 +464,16 @@ void zero_bytes(hipStream_t st, void* base, size_t bytes)
 {
     if (!bytes) return;
     const int64_t n = (int64_t)(bytes / 4);
+    if (recording()) { record(FWI_K_FILL, dim3(grid_for(n, 256, 8192)), dim3(256), 0); return; }
     hipLaunchKernelGGL(zero_kernel<uint32_t>, dim3(grid_for(n, 256, 8192)), dim3(256), 0, st,
                        reinterpret_cast<uint32_t*>(base), n);
+}
+
+// Clear n status or barrier words.
+void zero_words(hipStream_t st, unsigned* w, int64_t n)
+{
+    if (recording()) { record(FWI_K_FILL, dim3(1), dim3(64), 0); return; }
+    hipLaunchKernelGGL(zero_kernel<unsigned>, dim3(1), dim3(64), 0, st, w, n);
 }
 
 }  // namespace
@@ -465,6 +527,11 @@ static fwi_status create_impl(fwi_plan* p, fwi_dtype dtype, const fwi_grid* grid
     if (o.persistent && o.mode != FWI_BATCHED) return fail(p, FWI_ERR_INVALID, "persistent requires FWI_BATCHED");
     if (o.barrier_spin < 0) return fail(p, FWI_ERR_INVALID, "barrier_spin must be >= 0");
     if (o.order != 0 && o.order != 2 && o.order != 4) return fail(p, FWI_ERR_INVALID, "order must be 0, 2 or 4");
+    if (o.hvp != 0 && o.hvp != 1) return fail(p, FWI_ERR_INVALID, "hvp must be 0 or 1");
+    if (o.host_only != 0 && o.host_only != 1) return fail(p, FWI_ERR_INVALID, "host_only must be 0 or 1");
+    if (o.hvp && (o.order == 4 || o.persistent || o.use_graph || o.forward_only || o.steps_per_launch > 1))
+        return fail(p, FWI_ERR_INVALID, "hvp plans run the second-order operator one step per launch, "
+                                        "not persistent, without graph, not forward-only");
     if (o.order == 4) {
         if (o.persistent) return fail(p, FWI_ERR_INVALID, "the fourth-order operator has no persistent form");
         if (o.steps_per_launch >= 2) return fail(p, FWI_ERR_INVALID, "the fourth-order operator runs one step per launch");
@@ -510,7 +577,7 @@ static fwi_status create_impl(fwi_plan* p, fwi_dtype dtype, const fwi_grid* grid
         p->rows = o.rows ? o.rows : 2;
         if (!two_step_ok(p->rows))
             return fail(p, FWI_ERR_INVALID, "two steps per launch need rows of 1, 2 or 4 whose tile fits the LDS");
-    } else if (o.steps_per_launch == 1 || o.mode == FWI_PLAIN) {
+    } else if (o.steps_per_launch == 1 || o.mode == FWI_PLAIN || o.hvp) {
         p->S = 1;
         p->rows = o.rows ? o.rows : 4;
     } else {
@@ -520,8 +587,10 @@ static fwi_status create_impl(fwi_plan* p, fwi_dtype dtype, const fwi_grid* grid
         p->S = two_step_ok(p->rows) ? (o.persistent ? 2 : 3) : 1;
     }
     p->acc_double = dtype == FWI_F64 || o.acc_double;
-    p->tsize = dtype == FWI_F64 ? 8 : 4;
-    p->asize = p->acc_double ? 8 : 4;
+    p->hvp = o.hvp != 0;
+    // an hvp plan stores (value, derivative) pairs in every field, coefficient and accumulator
+    p->tsize = (dtype == FWI_F64 ? 8 : 4) * (p->hvp ? 2 : 1);
+    p->asize = (p->acc_double ? 8 : 4) * (p->hvp ? 2 : 1);
     const int G = p->G, rows = p->rows;
     const int tile_rows = kWavesZ * rows;
 
@@ -558,6 +627,8 @@ static fwi_status create_impl(fwi_plan* p, fwi_dtype dtype, const fwi_grid* grid
 
     // ---------------- checkpoint intervals and waves under the memory budget
     double budget = o.mem_budget;
+    if (o.host_only && !(budget > 0))
+        return fail(p, FWI_ERR_INVALID, "a host-only plan needs mem_budget > 0 (there is no device to ask)");
     if (budget <= 0) {
         size_t fr = 0, tot = 0;
         HIPCHK(p, hipMemGetInfo(&fr, &tot));
@@ -597,9 +668,13 @@ static fwi_status create_impl(fwi_plan* p, fwi_dtype dtype, const fwi_grid* grid
         size_t zmax = 0;
         for (auto& it : p->items) zmax = std::max(zmax, plane_bytes(it));
         fixed += zmax + align_up((size_t)n_media * kMisfitBlocks * sizeof(double));
-        for (auto& m : p->media)
+        for (auto& m : p->media) {
             fixed += align_up((size_t)m.acc_slots * 2 * m.g.nx * m.g.nz * p->asize) +
                      align_up((size_t)2 * m.g.nx * m.g.nz * p->tsize);
+            if (p->hvp)
+                fixed += align_up((size_t)m.g.n_tx * m.g.nt * p->tsize) +
+                         2 * align_up((size_t)m.g.n_tx * m.g.nt * m.g.n_rcv * p->tsize);
+        }
     }
     const double state_budget = budget - (double)fixed;
     if (o.forward_only)
@@ -695,6 +770,13 @@ static fwi_status create_impl(fwi_plan* p, fwi_dtype dtype, const fwi_grid* grid
     p->partial_off = off;
     off += align_up((size_t)n_media * kMisfitBlocks * sizeof(double));
     for (auto& m : p->media) { m.coef_off = off; off += align_up((size_t)2 * m.g.nx * m.g.nz * p->tsize); }
+    if (p->hvp)
+        for (auto& m : p->media) {
+            const size_t ntr = (size_t)m.g.n_tx * m.g.nt * m.g.n_rcv * p->tsize;
+            m.wav_off = off; off += align_up((size_t)m.g.n_tx * m.g.nt * p->tsize);
+            m.obs_off = off; off += align_up(ntr);
+            m.trd_off = off; off += align_up(ntr);
+        }
     const size_t state_off = off;
     size_t state_max = 0;
     for (auto& w : p->waves) {
@@ -734,7 +816,22 @@ static fwi_status create_impl(fwi_plan* p, fwi_dtype dtype, const fwi_grid* grid
         std::vector<double> ex(m.g.nx), ez(m.g.nz);
         for (int i = 0; i < m.g.nx; ++i) ex[i] = prof(i, m.g.nx, m.g.npml, m.dmax) * m.g.dt;
         for (int i = 0; i < m.g.nz; ++i) ez[i] = prof(i, m.g.nz, m.g.npml, m.dmax) * m.g.dt;
-        if (dtype == FWI_F64) {
+        if (p->hvp) {
+            // (value, derivative) pairs: the profiles do not depend on the medium
+            if (dtype == FWI_F64) {
+                std::vector<double> dx(2 * ex.size(), 0.0), dz(2 * ez.size(), 0.0);
+                for (size_t i = 0; i < ex.size(); ++i) dx[2 * i] = ex[i];
+                for (size_t i = 0; i < ez.size(); ++i) dz[2 * i] = ez[i];
+                m.ex_off = tab_put(dx.data(), dx.size() * 8);
+                m.ez_off = tab_put(dz.data(), dz.size() * 8);
+            } else {
+                std::vector<float> dx(2 * ex.size(), 0.0f), dz(2 * ez.size(), 0.0f);
+                for (size_t i = 0; i < ex.size(); ++i) dx[2 * i] = (float)ex[i];
+                for (size_t i = 0; i < ez.size(); ++i) dz[2 * i] = (float)ez[i];
+                m.ex_off = tab_put(dx.data(), dx.size() * 4);
+                m.ez_off = tab_put(dz.data(), dz.size() * 4);
+            }
+        } else if (dtype == FWI_F64) {
             m.ex_off = tab_put(ex.data(), ex.size() * 8);
             m.ez_off = tab_put(ez.data(), ez.size() * 8);
         } else {
@@ -867,12 +964,17 @@ static fwi_status create_impl(fwi_plan* p, fwi_dtype dtype, const fwi_grid* grid
     p->item_bytes = (p->dtype == FWI_F64 ? sizeof(Item<double, double>)
                      : p->acc_double ? sizeof(Item<float, double>) : sizeof(Item<float, float>)) * p->items.size();
     p->media_bytes = (p->dtype == FWI_F64 ? sizeof(MediumDev<double>) : sizeof(MediumDev<float>)) * p->media.size();
+    p->hvp_bytes = p->hvp ? (dtype == FWI_F64 ? sizeof(MediumHvp<double>) : sizeof(MediumHvp<float>)) * p->media.size()
+                          : 0;
     const size_t items_off = align_up(tab.size());
     const size_t media_off = align_up(items_off + p->item_bytes);
-    const size_t status_off = align_up(media_off + p->media_bytes);
+    const size_t hvp_off = align_up(media_off + p->media_bytes);
+    const size_t status_off = align_up(hvp_off + p->hvp_bytes);
     const size_t bar_off = status_off + kAlign;
     p->tables_bytes = bar_off + kAlign;
     tab.resize(p->tables_bytes, 0);
+    p->spin_limit = o.barrier_spin > 0 ? (unsigned)o.barrier_spin : (1u << 21);
+    if (o.host_only) return FWI_OK;      // no device tables: sizes and launch lists only
 
     HIPCHK(p, hipMalloc(&p->d_tables, p->tables_bytes));
     HIPCHK(p, hipMemcpy(p->d_tables, tab.data(), p->tables_bytes, hipMemcpyHostToDevice));
@@ -880,11 +982,12 @@ static fwi_status create_impl(fwi_plan* p, fwi_dtype dtype, const fwi_grid* grid
     p->d_blocks = reinterpret_cast<int2*>(base + blocks_off);
     p->d_items = base + items_off;
     p->d_media = base + media_off;
+    p->d_hvp = p->hvp ? base + hvp_off : nullptr;
     p->d_status = reinterpret_cast<unsigned*>(base + status_off);
     p->d_bar = reinterpret_cast<unsigned*>(base + bar_off);
-    p->spin_limit = o.barrier_spin > 0 ? (unsigned)o.barrier_spin : (1u << 21);
     if (o.persistent) HIPCHK(p, persistent_grid(p, &p->pgrid));
-    HIPCHK(p, hipHostMalloc(&p->h_stage, align_up(p->item_bytes) + align_up(p->media_bytes), hipHostMallocDefault));
+    HIPCHK(p, hipHostMalloc(&p->h_stage, align_up(p->item_bytes) + align_up(p->media_bytes) + align_up(p->hvp_bytes),
+                            hipHostMallocDefault));
     HIPCHK(p, allow_lds_plan(p));
     HIPCHK(p, hipEventCreateWithFlags(&p->stage_ev, hipEventDisableTiming));
     return FWI_OK;
@@ -952,13 +1055,12 @@ extern "C" fwi_status fwi_plan_get_info(const fwi_plan* p, fwi_plan_info* info)
 
 namespace {
 
-enum Call { kExecute = 0, kForward = 1, kAdjoint = 2 };
+enum Call { kExecute = 0, kForward = 1, kAdjoint = 2, kHvp = 3 };
 
 template <typename T, typename Acc>
-void fill_descriptors(fwi_plan* p, const fwi_io* io, unsigned char* ws, bool adj_from_dadj)
+void fill_items(fwi_plan* p, const fwi_io* io, unsigned char* ws, bool adj_from_dadj)
 {
     auto* items = reinterpret_cast<Item<T, Acc>*>(p->h_stage);
-    auto* media = reinterpret_cast<MediumDev<T>*>(reinterpret_cast<unsigned char*>(p->h_stage) + align_up(p->item_bytes));
     auto* tabs = reinterpret_cast<unsigned char*>(p->d_tables);
     for (size_t i = 0; i < p->items.size(); ++i) {
         const ItemPlan& ip = p->items[i];
@@ -995,8 +1097,22 @@ void fill_descriptors(fwi_plan* p, const fwi_io* io, unsigned char* ws, bool adj
         d.nlam = p->nlam;
         // the adjoint of the last segment reads levels (J-1)K + 1 .. T of the first pass
         d.keep_from = p->opt.forward_only ? INT_MAX : (ip.J - 1) * ip.K + 1;
+        if (p->hvp) {
+            // the dual kernels read and write the dual copies in the workspace
+            d.wavelet = reinterpret_cast<const T*>(ws + m.wav_off);
+            d.traces = reinterpret_cast<T*>(ws + m.trd_off);
+            d.d_obs = reinterpret_cast<const T*>(ws + m.obs_off);
+            d.d_adj = nullptr;
+            d.inject_adj = 0;
+        }
         items[i] = d;
     }
+}
+
+template <typename T>
+void fill_media(fwi_plan* p, const fwi_io* io, unsigned char* ws)
+{
+    auto* media = reinterpret_cast<MediumDev<T>*>(reinterpret_cast<unsigned char*>(p->h_stage) + align_up(p->item_bytes));
     for (size_t i = 0; i < p->media.size(); ++i) {
         const MediumPlan& m = p->media[i];
         const fwi_io& mio = io[i];
@@ -1020,6 +1136,62 @@ void fill_descriptors(fwi_plan* p, const fwi_io* io, unsigned char* ws, bool adj
     }
 }
 
+template <typename T>
+void fill_hvp(fwi_plan* p, const fwi_io* io, const fwi_hvp_io* dir, unsigned char* ws)
+{
+    auto* hv = reinterpret_cast<MediumHvp<T>*>(reinterpret_cast<unsigned char*>(p->h_stage) + align_up(p->item_bytes) +
+                                               align_up(p->media_bytes));
+    for (size_t i = 0; i < p->media.size(); ++i) {
+        const MediumPlan& m = p->media[i];
+        const fwi_io& mio = io[i];
+        MediumHvp<T> d{};
+        d.nx = m.g.nx; d.nz = m.g.nz; d.n_tx = m.g.n_tx; d.nt = m.g.nt;
+        d.n_rcv = m.g.n_rcv; d.npml = m.g.npml; d.acc_slots = m.acc_slots; d.wavelet_shared = mio.wavelet_shared ? 1 : 0;
+        d.h = m.g.h; d.dt = m.g.dt; d.dmax = m.dmax; d.c_max = m.g.c_max;
+        d.acc_stride = 2LL * m.g.nx * m.g.nz;
+        d.c = reinterpret_cast<const T*>(mio.c);
+        d.rho = reinterpret_cast<const T*>(mio.rho);
+        d.dc = reinterpret_cast<const T*>(dir[i].dc);
+        d.drho = reinterpret_cast<const T*>(dir[i].drho);
+        d.wavelet = reinterpret_cast<const T*>(mio.wavelet);
+        d.d_obs = reinterpret_cast<const T*>(mio.d_obs);
+        d.traces = reinterpret_cast<T*>(mio.traces);
+        d.dtraces = reinterpret_cast<T*>(dir[i].dtraces);
+        d.grad_c = reinterpret_cast<T*>(mio.grad_c);
+        d.grad_rho = reinterpret_cast<T*>(mio.grad_rho);
+        d.hv_c = reinterpret_cast<T*>(dir[i].hv_c);
+        d.hv_rho = reinterpret_cast<T*>(dir[i].hv_rho);
+        d.coef = reinterpret_cast<Dual<T>*>(ws + m.coef_off);
+        d.wav = reinterpret_cast<Dual<T>*>(ws + m.wav_off);
+        d.obs = reinterpret_cast<Dual<T>*>(ws + m.obs_off);
+        d.tr = reinterpret_cast<Dual<T>*>(ws + m.trd_off);
+        d.acc0 = ws + m.acc_off;
+        hv[i] = d;
+    }
+}
+
+void fill_descriptors(fwi_plan* p, const fwi_io* io, const fwi_hvp_io* dir, unsigned char* ws, bool adj_from_dadj)
+{
+    if (p->hvp) {
+        if (p->dtype == FWI_F64) {
+            fill_items<Dual<double>, Dual<double>>(p, io, ws, false);
+            fill_media<double>(p, io, ws);
+            fill_hvp<double>(p, io, dir, ws);
+        } else {
+            if (p->acc_double) fill_items<Dual<float>, Dual<double>>(p, io, ws, false);
+            else fill_items<Dual<float>, Dual<float>>(p, io, ws, false);
+            fill_media<float>(p, io, ws);
+            fill_hvp<float>(p, io, dir, ws);
+        }
+        return;
+    }
+    if (p->dtype == FWI_F64) fill_items<double, double>(p, io, ws, adj_from_dadj);
+    else if (p->acc_double) fill_items<float, double>(p, io, ws, adj_from_dadj);
+    else fill_items<float, float>(p, io, ws, adj_from_dadj);
+    if (p->dtype == FWI_F64) fill_media<double>(p, io, ws);
+    else fill_media<float>(p, io, ws);
+}
+
 template <typename T, typename Acc>
 void enqueue_medium(fwi_plan* p, hipStream_t st, int which, unsigned char* ws)
 {
@@ -1028,6 +1200,14 @@ void enqueue_medium(fwi_plan* p, hipStream_t st, int which, unsigned char* ws)
     for (auto& m : p->media) nmax = std::max<int64_t>(nmax, (int64_t)m.g.nx * m.g.nz);
     const auto* md = reinterpret_cast<const MediumDev<T>*>(p->d_media);
     const dim3 g2(grid_for(nmax, 256, 2048), nm);
+    if (recording()) {
+        if (which == 0) record(FWI_K_PREP, g2, dim3(256), 0);
+        else if (which == 1) {
+            record(FWI_K_MISFIT_PARTIAL, dim3(kMisfitBlocks, nm), dim3(256), 0);
+            record(FWI_K_MISFIT_FINAL, dim3((nm + 63) / 64), dim3(64), 0);
+        } else record(FWI_K_FINALIZE, g2, dim3(256), 0);
+        return;
+    }
     if (which == 0) {
         hipLaunchKernelGGL(prep_kernel<T>, g2, dim3(256), 0, st, md, p->d_status);
     } else if (which == 1) {
@@ -1050,7 +1230,7 @@ void medium_kernels(fwi_plan* p, hipStream_t st, int which, unsigned char* ws)
 // The whole launch sequence of one call on stream st (no host synchronisation).
 void enqueue_sequence(fwi_plan* p, hipStream_t st, unsigned char* ws, int call, bool want_grad)
 {
-    hipLaunchKernelGGL(zero_kernel<unsigned>, dim3(1), dim3(64), 0, st, p->d_status, (int64_t)1);
+    zero_words(st, p->d_status, 1);
     // an execute without gradient outputs is a forward solve (+ misfit)
     if (call == kExecute && !want_grad) call = kForward;
     if (call != kAdjoint) {
@@ -1062,9 +1242,10 @@ void enqueue_sequence(fwi_plan* p, hipStream_t st, unsigned char* ws, int call, 
     const int mode = call == kExecute ? kRunAll : call == kForward ? kRunFwdOnly : kRunAdjOnly;
     for (const Wave& w : p->waves) {
         const int S = call == kExecute ? w.steps : call == kForward ? w.fwd : w.adj;
+        g_rec.wave = (int)(&w - p->waves.data());
         if (call != kForward) zero_bytes(st, ws + w.lam_off, w.lam_bytes);
         if (p->opt.persistent) {
-            hipLaunchKernelGGL(zero_kernel<unsigned>, dim3(1), dim3(64), 0, st, p->d_bar, (int64_t)4);
+            zero_words(st, p->d_bar, 4);
             launch_persistent(p, st, w, call == kExecute ? 0 : call == kForward ? 1 : 2, mode);
             continue;
         }
@@ -1072,19 +1253,126 @@ void enqueue_sequence(fwi_plan* p, hipStream_t st, unsigned char* ws, int call, 
             int n_active = 0;
             const unsigned kinds = wave_kinds(p, w, s, mode, &n_active);
             const dim3 grid((unsigned)w.prefix[n_active]);
+            g_rec.step = s;
             for (int k = 0; k < 5; ++k)
                 if (kinds & (1u << k)) step(p, k, grid, st, p->d_blocks + w.blk0, s, mode);
         }
+        g_rec.step = -1;
     }
+    g_rec.wave = -1;
     if (call != kAdjoint) medium_kernels(p, st, 1, ws);
     if (call != kForward) medium_kernels(p, st, 2, ws);
 }
 
-fwi_status run_call(fwi_plan* p, const fwi_io* io, void* workspace, size_t bytes, void* stream, int call)
+// One-step dual kernels of an hvp plan (kind 0 forward-type, 2 adjoint).
+template <typename T, typename Acc>
+void step_hvp_t(int G, int kind, dim3 grid, hipStream_t st, const void* items, const int2* blocks, int s, int rows)
+{
+    const dim3 blk(kTileX, kWavesZ);
+    auto go = [&](auto g) {
+        constexpr int GG = decltype(g)::value;
+        const auto* it = reinterpret_cast<const Item<T, Acc>*>(items);
+        if (kind == 0) hipLaunchKernelGGL((fwd1_kernel<T, GG, Acc>), grid, blk, 0, st, it, blocks, s, (int)kRunAll, rows);
+        else hipLaunchKernelGGL((adj1_kernel<T, GG, Acc>), grid, blk, 0, st, it, blocks, s, (int)kRunAll, rows);
+    };
+    if (G == 1) go(std::integral_constant<int, 1>());
+    else if (G == 2) go(std::integral_constant<int, 2>());
+    else go(std::integral_constant<int, 4>());
+}
+
+void step_hvp(fwi_plan* p, int kind, dim3 grid, hipStream_t st, const int2* blocks, int s)
+{
+    if (recording()) { record(kind == 0 ? FWI_K_FWD1 : FWI_K_ADJ1, grid, dim3(kTileX, kWavesZ), 0); return; }
+    if (p->dtype == FWI_F64) step_hvp_t<Dual<double>, Dual<double>>(p->G, kind, grid, st, p->d_items, blocks, s, p->rows);
+    else if (p->acc_double) step_hvp_t<Dual<float>, Dual<double>>(p->G, kind, grid, st, p->d_items, blocks, s, p->rows);
+    else step_hvp_t<Dual<float>, Dual<float>>(p->G, kind, grid, st, p->d_items, blocks, s, p->rows);
+}
+
+template <typename T, typename A>
+void hvp_medium(fwi_plan* p, hipStream_t st, int which)
+{
+    const int nm = (int)p->media.size();
+    int64_t nmax = 0, tmax = 0;
+    for (auto& m : p->media) {
+        nmax = std::max<int64_t>(nmax, (int64_t)m.g.nx * m.g.nz);
+        tmax = std::max<int64_t>(tmax, (int64_t)m.g.n_tx * m.g.nt * (m.g.n_rcv + 1));
+    }
+    const auto* md = reinterpret_cast<const MediumHvp<T>*>(p->d_hvp);
+    if (recording()) {
+        if (which == 0) {
+            record(FWI_K_PREP_HVP, dim3(grid_for(nmax, 256, 2048), nm), dim3(256), 0);
+            record(FWI_K_PACK_HVP, dim3(grid_for(tmax, 256, 2048), nm), dim3(256), 0);
+        } else if (which == 1) {
+            record(FWI_K_UNPACK_HVP, dim3(grid_for(tmax, 256, 2048), nm), dim3(256), 0);
+        } else {
+            record(FWI_K_FINALIZE_HVP, dim3(grid_for(nmax, 256, 2048), nm), dim3(256), 0);
+        }
+        return;
+    }
+    if (which == 0) {
+        hipLaunchKernelGGL(prep_hvp_kernel<T>, dim3(grid_for(nmax, 256, 2048), nm), dim3(256), 0, st, md, p->d_status);
+        hipLaunchKernelGGL(pack_hvp_kernel<T>, dim3(grid_for(tmax, 256, 2048), nm), dim3(256), 0, st, md);
+    } else if (which == 1) {
+        hipLaunchKernelGGL(unpack_hvp_kernel<T>, dim3(grid_for(tmax, 256, 2048), nm), dim3(256), 0, st, md);
+    } else {
+        hipLaunchKernelGGL((finalize_hvp_kernel<T, A>), dim3(grid_for(nmax, 256, 2048), nm), dim3(256), 0, st, md,
+                           p->d_status);
+    }
+}
+
+void hvp_medium_kernels(fwi_plan* p, hipStream_t st, int which)
+{
+    if (p->dtype == FWI_F64) hvp_medium<double, double>(p, st, which);
+    else if (p->acc_double) hvp_medium<float, double>(p, st, which);
+    else hvp_medium<float, float>(p, st, which);
+}
+
+// The launch sequence of fwi_plan_hvp: dual coefficients and inputs, the
+// dual gradient schedule of every wave, then traces, misfit and the gradient
+// with its derivative.
+void enqueue_hvp(fwi_plan* p, hipStream_t st, unsigned char* ws)
+{
+    zero_words(st, p->d_status, 1);
+    zero_bytes(st, ws + p->clear_off, p->clear_bytes);
+    hvp_medium_kernels(p, st, 0);
+    for (const Wave& w : p->waves) {
+        g_rec.wave = (int)(&w - p->waves.data());
+        zero_bytes(st, ws + w.lam_off, w.lam_bytes);
+        for (int s = 0; s < w.steps; ++s) {
+            int n_active = 0;
+            const unsigned kinds = wave_kinds(p, w, s, kRunAll, &n_active);
+            const dim3 grid((unsigned)w.prefix[n_active]);
+            g_rec.step = s;
+            if (kinds & 1u) step_hvp(p, 0, grid, st, p->d_blocks + w.blk0, s);
+            if (kinds & 4u) step_hvp(p, 2, grid, st, p->d_blocks + w.blk0, s);
+        }
+        g_rec.step = -1;
+    }
+    g_rec.wave = -1;
+    hvp_medium_kernels(p, st, 1);
+    medium_kernels(p, st, 1, ws);       // misfit of the primal traces
+    hvp_medium_kernels(p, st, 2);
+}
+
+// allow_graph = false: eager launches only and no replay state recorded for
+// the workspace (the no-allocation variant, whose workspace callers never see).
+fwi_status run_call(fwi_plan* p, const fwi_io* io, void* workspace, size_t bytes, void* stream, int call,
+                    bool allow_graph = true, const fwi_hvp_io* dir = nullptr)
 {
     if (!p) return FWI_ERR_INVALID;
     p->last_error.clear();
+    if (p->opt.host_only) return fail(p, FWI_ERR_INVALID, "host-only plan: no device calls");
     if (!io) return fail(p, FWI_ERR_INVALID, "io must be non-NULL");
+    if (p->hvp != (call == kHvp))
+        return fail(p, FWI_ERR_INVALID, p->hvp ? "this plan was created for fwi_plan_hvp (options.hvp = 1)"
+                                               : "fwi_plan_hvp needs a plan created with options.hvp = 1");
+    if (call == kHvp) {
+        if (!dir) return fail(p, FWI_ERR_INVALID, "dir must be non-NULL");
+        for (size_t i = 0; i < p->media.size(); ++i) {
+            if (!dir[i].dc || !dir[i].hv_c) return fail(p, FWI_ERR_INVALID, "dc and hv_c are required");
+            if (!io[i].d_obs) return fail(p, FWI_ERR_INVALID, "a Hessian-vector product needs d_obs");
+        }
+    }
     if (!workspace || bytes < p->ws_bytes) return fail(p, FWI_ERR_WORKSPACE, "workspace missing or too small");
     if ((reinterpret_cast<uintptr_t>(workspace) & (kAlign - 1)) != 0)
         return fail(p, FWI_ERR_WORKSPACE, "workspace must be 256-byte aligned");
@@ -1105,7 +1393,7 @@ fwi_status run_call(fwi_plan* p, const fwi_io* io, void* workspace, size_t bytes
         return fail(p, FWI_ERR_INVALID, "forward-only plan: no adjoint or gradient");
     if (call == kAdjoint && std::find(p->fwd_ws.begin(), p->fwd_ws.end(), workspace) == p->fwd_ws.end())
         return fail(p, FWI_ERR_STATE, "no forward state in this workspace");
-    if (call != kExecute && p->waves.size() > 1)
+    if (call != kExecute && call != kHvp && p->waves.size() > 1)
         return fail(p, FWI_ERR_INVALID, "forward/adjoint need every item resident at once: use FWI_BATCHED "
                                         "with a memory budget that holds all items");
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
@@ -1113,15 +1401,23 @@ fwi_status run_call(fwi_plan* p, const fwi_io* io, void* workspace, size_t bytes
 
     // descriptors: reuse the pinned staging buffer once the previous upload has been consumed
     if (p->stage_pending) HIPCHK(p, hipEventSynchronize(p->stage_ev));
-    if (p->dtype == FWI_F64) fill_descriptors<double, double>(p, io, ws, dadj);
-    else if (p->acc_double) fill_descriptors<float, double>(p, io, ws, dadj);
-    else fill_descriptors<float, float>(p, io, ws, dadj);
-    HIPCHK(p, hipMemcpyAsync(p->d_items, p->h_stage, align_up(p->item_bytes) + p->media_bytes,
+    fill_descriptors(p, io, dir, ws, dadj);
+    HIPCHK(p, hipMemcpyAsync(p->d_items, p->h_stage,
+                             p->hvp ? align_up(p->item_bytes) + align_up(p->media_bytes) + p->hvp_bytes
+                                    : align_up(p->item_bytes) + p->media_bytes,
                              hipMemcpyHostToDevice, st));
     HIPCHK(p, hipEventRecord(p->stage_ev, st));
     p->stage_pending = true;
 
-    const bool graph = p->opt.use_graph && call == kExecute;
+    const bool graph = allow_graph && p->opt.use_graph && call == kExecute;
+    if (call == kHvp) {
+        enqueue_hvp(p, st, ws);
+        HIPCHK(p, hipGetLastError());
+        p->last_stream = st;
+        p->have_call = true;
+        p->fwd_ws.erase(std::remove(p->fwd_ws.begin(), p->fwd_ws.end(), workspace), p->fwd_ws.end());
+        return FWI_OK;
+    }
     if (graph) {
         const unsigned flags = want_grad ? 1u : 0u;
         if (!p->gexec || p->graph_ws != workspace || p->graph_flags != flags) {
@@ -1146,7 +1442,7 @@ fwi_status run_call(fwi_plan* p, const fwi_io* io, void* workspace, size_t bytes
     p->have_call = true;
     // a forward leaves replay state in its workspace; any other call consumes or overwrites it
     p->fwd_ws.erase(std::remove(p->fwd_ws.begin(), p->fwd_ws.end(), workspace), p->fwd_ws.end());
-    if (call == kForward || (call == kExecute && !want_grad)) p->fwd_ws.push_back(workspace);
+    if (allow_graph && (call == kForward || (call == kExecute && !want_grad))) p->fwd_ws.push_back(workspace);
     return FWI_OK;
 }
 
@@ -1167,6 +1463,34 @@ extern "C" fwi_status fwi_plan_adjoint(fwi_plan* p, const fwi_io* io, void* ws, 
     return run_call(p, io, ws, bytes, stream, kAdjoint);
 }
 
+extern "C" fwi_status fwi_plan_hvp(fwi_plan* p, const fwi_io* io, const fwi_hvp_io* dir, void* ws, size_t bytes,
+                                   void* stream)
+{
+    return run_call(p, io, ws, bytes, stream, kHvp, true, dir);
+}
+
+extern "C" fwi_status fwi_plan_launches(const fwi_plan* cp, int32_t call, fwi_launch* out, int64_t capacity,
+                                        int64_t* count)
+{
+    if (!cp || !count || capacity < 0 || (capacity > 0 && !out) || call < 0 || call > 3) return FWI_ERR_INVALID;
+    fwi_plan* p = const_cast<fwi_plan*>(cp);
+    if (p->hvp != (call == 3)) return fail(p, FWI_ERR_INVALID, "call does not match the plan (hvp)");
+    if (p->opt.forward_only && call != 1) return fail(p, FWI_ERR_INVALID, "forward-only plan: forward calls only");
+    if ((call == 1 || call == 2) && p->waves.size() > 1)
+        return fail(p, FWI_ERR_INVALID, "forward/adjoint need every item resident at once");
+    std::vector<fwi_launch> v;
+    g_rec = LaunchRec{&v, -1, -1};
+    // addresses are never formed into device pointers while recording
+    unsigned char* ws = reinterpret_cast<unsigned char*>(kAlign);
+    if (call == 3) enqueue_hvp(p, nullptr, ws);
+    else enqueue_sequence(p, nullptr, ws, call == 0 ? kExecute : call == 1 ? kForward : kAdjoint, call == 0);
+    g_rec = LaunchRec{};
+    *count = (int64_t)v.size();
+    const int64_t nw = std::min<int64_t>(capacity, (int64_t)v.size());
+    for (int64_t i = 0; i < nw; ++i) out[i] = v[(size_t)i];
+    return FWI_OK;
+}
+
 extern "C" fwi_status fwi_plan_check(fwi_plan* p)
 {
     if (!p) return FWI_ERR_INVALID;
@@ -1178,7 +1502,7 @@ extern "C" fwi_status fwi_plan_check(fwi_plan* p)
     if (flags & kFlagMedium) return fail(p, FWI_ERR_MEDIUM, "c or rho not positive and finite");
     if (flags & kFlagCfl) return fail(p, FWI_ERR_CFL, "a cell's c exceeds the declared c_max");
     if (flags & kFlagBarrier) return fail(p, FWI_ERR_HIP, "persistent grid barrier abandoned after its spin limit");
-    if (flags & kFlagNonfinite) return fail(p, FWI_ERR_NONFINITE, "non-finite misfit or gradient");
+    if (flags & kFlagNonfinite) return fail(p, FWI_ERR_NONFINITE, "non-finite traces, misfit or gradient");
     return FWI_OK;
 }
 

@@ -1,9 +1,13 @@
 """The benchmark workload at full size, in the launch configuration bench.py
-times (64 uneven media in one batched plan, two steps per launch, 64 x 8
-tiles, groups of 4 transmits, checkpointed replay under an 85 % memory
-budget), checked on outputs the oracle computes in seconds: the traces of
-two transmits of the largest medium, and the traces, misfit and gradient of
-the medium with the fewest cell-updates."""
+times (64 uneven media in one batched plan, three forward and two adjoint
+steps per launch, 64 x 8 tiles, groups of 4 transmits, checkpointed replay
+under an 85 % memory budget), checked on outputs the oracle computes in a
+minute: the medium with the fewest cell-updates (traces, misfit, gradient
+over all its transmits), and the largest medium (768-class grid, longest
+schedule) with its first and last transmits driven by the Ricker pulse and
+observed data, its other transmits by a zero wavelet and zero observed data
+(zero fields and residuals: the plan and its launches are unchanged, and
+the medium's gradient is the two transmits' sum)."""
 import numpy as np
 import pytest
 
@@ -24,7 +28,18 @@ def test_uneven64_full_size_sampled():
     # medium, zero elsewhere (no input comes from the library)
     partner = W.partner_medium(media[small], 7000 + small)
     obs_small = oracle_obs(partner)
-    c_max = 1.02 * max(float(np.max(m.c)) for m in media + [partner])
+    mb = media[big]
+    tx = [0, mb.geom.n_tx - 1]
+    keep = np.zeros(mb.geom.n_tx, bool)
+    keep[tx] = True
+    mb.wavelet = np.where(keep[:, None], mb.wavelet, 0.0).astype(np.float32)
+    partner_big = W.partner_medium(mb, 7000 + big)
+    print(f"[fullsize] oracle: observed traces of medium {big} ({mb.geom.nx}^2 x {mb.geom.nt}), transmits {tx}",
+          flush=True)
+    obs_big2 = oracle_obs(subset(partner_big, tx))
+    obs_big = np.zeros((mb.geom.n_tx, mb.geom.nt, mb.geom.n_rcv), np.float32)
+    obs_big[tx] = obs_big2
+    c_max = 1.02 * max(float(np.max(m.c)) for m in media + [partner, partner_big])
     grids = [F.GridSpec.of(m.geom, c_max) for m in media]
     torch.cuda.empty_cache()
     free, _ = torch.cuda.mem_get_info()
@@ -36,7 +51,8 @@ def test_uneven64_full_size_sampled():
     ios = []
     for i, (g, m) in enumerate(zip(grids, media)):
         ios.append({"c": t(m.c), "rho": t(m.rho), "wavelet": t(m.wavelet),
-                    "d_obs": t(obs_small) if i == small else torch.zeros((g.n_tx, g.nt, g.n_rcv), device=dev),
+                    "d_obs": (t(obs_small) if i == small else t(obs_big) if i == big
+                              else torch.zeros((g.n_tx, g.nt, g.n_rcv), device=dev)),
                     "traces": torch.empty((g.n_tx, g.nt, g.n_rcv), device=dev),
                     "grad_c": torch.empty((g.nz, g.nx), device=dev),
                     "grad_rho": torch.empty((g.nz, g.nx), device=dev),
@@ -46,17 +62,19 @@ def test_uneven64_full_size_sampled():
     plan.check()
     print(f"plan: waves {info['waves']}, K {info['min_ckpt']}..{info['max_ckpt']}, "
           f"launches {info['launches']}; checked media: small {small} {media[small].name}, big {big} {media[big].name}")
-    # traces of the first and last transmit of the largest medium
-    mb = media[big]
-    tx = [0, mb.geom.n_tx - 1]
-    ref = oracle_obs(subset(mb, tx))
-    got = ios[big]["traces"].cpu().numpy()[tx]
-    e_tr = rel_l2(got, ref)
+    # the largest medium: the two driven transmits' traces, misfit and gradient
+    print(f"[fullsize] oracle: gradient of medium {big}, transmits {tx}", flush=True)
+    rb = oracle_grad(subset(mb, tx), obs_big2, ckpt=100)
+    got = ios[big]["traces"].cpu().numpy()
+    assert np.all(got[~keep] == 0.0)
+    eb = {k: rel_l2(ios[big][k].cpu().numpy(), rb[k]) for k in ("grad_c", "grad_rho")}
+    eb["traces"] = rel_l2(got[tx], rb["traces"])
+    eb["misfit"] = abs(float(ios[big]["misfit"]) - rb["misfit"]) / rb["misfit"]
     # the smallest medium: traces, misfit, gradients
     r = oracle_grad(media[small], obs_small)
     e = {k: rel_l2(ios[small][k].cpu().numpy(), r[k]) for k in ("traces", "grad_c", "grad_rho")}
-    e_j = abs(float(ios[small]["misfit"]) - r["misfit"]) / r["misfit"]
-    print("largest medium traces", e_tr, "smallest medium", e, "misfit", e_j)
-    assert e_tr <= 1e-5
-    assert e["traces"] <= 1e-5
-    assert e["grad_c"] <= 1e-4 and e["grad_rho"] <= 1e-4 and e_j <= 1e-4
+    e["misfit"] = abs(float(ios[small]["misfit"]) - r["misfit"]) / r["misfit"]
+    print("largest medium", eb, "smallest medium", e, flush=True)
+    for err in (eb, e):
+        assert err["traces"] <= 1e-5
+        assert err["grad_c"] <= 1e-4 and err["grad_rho"] <= 1e-4 and err["misfit"] <= 1e-4

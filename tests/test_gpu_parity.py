@@ -109,14 +109,20 @@ def test_forward_adjoint_with_given_source():
 
 
 def test_graph_replay_matches_eager():
-    """The hipGraph replay gives bitwise the eager results on every replay."""
+    """The hipGraph replay gives bitwise the eager results on every replay,
+    and every replay meets the FP32 bars against the oracle."""
     m = W.small_random_medium(21, 100, 60, 100, n_tx=4, n_rcv=5, npml=3)
     obs = _observed(m, 3)
+    ref = oracle_grad(m, obs)
     eager, _ = gpu_run([m], [obs], dtype="f32", ckpt=9)
     reps, _ = gpu_run([m], [obs], dtype="f32", ckpt=9, use_graph=True, reps=3)
     for r in reps:
         for k in ("traces", "grad_c", "grad_rho", "misfit"):
             assert np.array_equal(r[0][k], eager[0][k]), k
+        assert rel_l2(r[0]["traces"], ref["traces"]) <= 1e-5
+        assert rel_l2(r[0]["grad_c"], ref["grad_c"]) <= 1e-4
+        assert rel_l2(r[0]["grad_rho"], ref["grad_rho"]) <= 1e-4
+        assert abs(float(r[0]["misfit"][0]) - ref["misfit"]) <= 1e-4 * ref["misfit"]
 
 
 def test_device_flags():
@@ -130,6 +136,28 @@ def test_device_flags():
     with pytest.raises(F.FwiError) as e:
         gpu_run([m], None, dtype="f32")
     assert e.value.status == 8
+
+
+@pytest.mark.parametrize("forward_only", [True, False])
+def test_nonfinite_traces_flagged(forward_only):
+    """A NaN wavelet sample makes the traces non-finite: a forward solve
+    without observed data (plain forward call or forward-only plan) reports
+    FWI_ERR_NONFINITE, and so does the autograd forward."""
+    import torch
+    import paper_2603_04070_amd as F
+    from paper_2603_04070_amd import autograd
+    m = W.small_random_medium(3, 70, 66, 40, n_tx=2, n_rcv=3, npml=3)
+    m.wavelet = m.wavelet.copy()
+    m.wavelet[1, 17] = np.nan
+    with pytest.raises(F.FwiError) as e:
+        gpu_run([m], None, dtype="f32", forward_only=forward_only)
+    assert e.value.status == 7 and "traces" in str(e.value)
+    if not forward_only:
+        plan = F.Plan([F.GridSpec.of(m.geom, float(m.c.max()) * 1.001)], dtype="f32")
+        t = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float32)).cuda()
+        with pytest.raises(F.FwiError) as e:
+            autograd.traces(plan, [t(m.c).requires_grad_()], [t(m.rho)], [t(m.wavelet)])
+        assert e.value.status == 7
 
 
 def test_rodgauss512_full_size_subset():
@@ -293,14 +321,17 @@ def test_persistent_matches_launch_per_step(spl):
 
 
 def test_persistent_graph_replays():
-    """The persistent launch recorded in a hipGraph: every replay equals the eager result."""
+    """The persistent launch recorded in a hipGraph: every replay equals the
+    eager result and meets the FP32 bars against the oracle."""
     media, obs = _two_media()
+    refs = [oracle_grad(m, o) for m, o in zip(media, obs)]
     eager, _ = gpu_run(media, obs, dtype="f32", ckpt=7)
     reps, _ = gpu_run(media, obs, dtype="f32", ckpt=7, persistent=True, use_graph=True, reps=3)
     for r in reps:
-        for a, b in zip(eager, r):
+        for a, b, ref in zip(eager, r, refs):
             for k in ("traces", "grad_c", "grad_rho", "misfit"):
                 assert np.array_equal(a[k], b[k]), k
+            _check(b, ref, "f32")
 
 
 def test_persistent_barrier_limit_reports_error():

@@ -19,11 +19,15 @@ Each test names what it pins:
   P12 mirror symmetry
   P13 checkpointed replay is bitwise store-all
   P14 stability bound: growth above it, bounded below
-  P15 absorbing-layer efficacy (reflection below -40 dB)
+  P15 absorbing-layer efficacy (reflection below -30 dB; a damping layer is not a PML)
   P16 fourth-order operator: its order of accuracy against closed-form
       Laplacians (constant and variable density)
   P17 fourth-order variant: Green's function, dot products, brute-force
       gradient, density-scale invariance, checkpoint replay, stability bound
+  P18 Hessian-vector product (differences of oracle gradients): at zero
+      residual it is 2 J^T J v (tangent-linear traces fed back through the
+      adjoint), it is symmetric, v^T H v is the second derivative of the
+      misfit along v, and it does not move with the difference step
 """
 import json
 import math
@@ -513,3 +517,60 @@ def test_p17_stability_bound_fourth_order():
         amps.append(np.max(np.abs(tr[-100:])))
     assert np.isfinite(amps[0]) and amps[0] < 10.0
     assert not np.isfinite(amps[1]) or amps[1] > 1e6
+
+
+# ---------------------------------------------------------------- P18 Hessian-vector product
+
+def _hvp_case():
+    m = W.small_random_medium(7, 24, 20, 90, n_tx=2, n_rcv=4, npml=3, courant=0.5, dup_receiver=True)
+    rng = np.random.default_rng(1)
+    v = (rng.standard_normal(m.c.shape) * 5.0, rng.standard_normal(m.c.shape) * 3.0)
+    u = (rng.standard_normal(m.c.shape) * 5.0, rng.standard_normal(m.c.shape) * 3.0)
+    mo = W.small_random_medium(8, 24, 20, 90, n_tx=2, n_rcv=4, npml=3, courant=0.5)
+    obs = O.run(m.geom, mo.c, mo.rho, m.wavelet)["traces"]
+    return m, v, u, obs
+
+
+def test_p18_hvp_zero_residual_is_gauss_newton():
+    """With d_obs = F(m) the residual vanishes and H = 2 J^T J: H v equals the
+    adjoint driven by twice the tangent-linear traces of v (eq. 6 with the
+    Born traces as the adjoint source), a code path that shares no
+    difference quotient with the Hessian-vector product."""
+    m, v, _, _ = _hvp_case()
+    g = m.geom
+    obs0 = O.run(g, m.c, m.rho, m.wavelet)["traces"]
+    h = O.hvp(g, m.c, m.rho, m.wavelet, obs0, *v)
+    dd = O.born(g, m.c, m.rho, m.wavelet, *v)
+    gn = O.run(g, m.c, m.rho, m.wavelet, d_adj=2.0 * dd)
+    assert rel_l2(h["hv_c"], gn["grad_c"]) <= 1e-9
+    assert rel_l2(h["hv_rho"], gn["grad_rho"]) <= 1e-9
+
+
+def test_p18_hvp_symmetric_and_second_derivative():
+    """<u, H v> = <v, H u>, and v^T H v = d^2/de^2 J(m + e v) at e = 0 (second
+    differences of the misfit alone, Richardson-extrapolated)."""
+    m, v, u, obs = _hvp_case()
+    g = m.geom
+    hv = O.hvp(g, m.c, m.rho, m.wavelet, obs, *v)
+    hu = O.hvp(g, m.c, m.rho, m.wavelet, obs, *u)
+    a = np.sum(u[0] * hv["hv_c"]) + np.sum(u[1] * hv["hv_rho"])
+    b = np.sum(v[0] * hu["hv_c"]) + np.sum(v[1] * hu["hv_rho"])
+    assert abs(a - b) <= 1e-10 * abs(a)
+    c0, r0 = m.c.astype(np.float64), m.rho.astype(np.float64)
+    J = lambda e: O.run(g, c0 + e * v[0], r0 + e * v[1], m.wavelet, d_obs=obs, gradient=False)["misfit"]
+    e = 1e-3 / max(np.max(np.abs(v[0]) / c0), np.max(np.abs(v[1]) / r0))
+    d2 = lambda e: (J(e) - 2 * J(0.0) + J(-e)) / (e * e)
+    vhv_j = (4 * d2(e / 2) - d2(e)) / 3
+    vhv = np.sum(v[0] * hv["hv_c"]) + np.sum(v[1] * hv["hv_rho"])
+    assert abs(vhv_j - vhv) <= 1e-8 * abs(vhv)
+
+
+def test_p18_hvp_step_plateau():
+    """The extrapolated differences agree across a hundredfold range of steps."""
+    m, v, _, obs = _hvp_case()
+    g = m.geom
+    ref = O.hvp(g, m.c, m.rho, m.wavelet, obs, *v)
+    for step in (1e-3, 1e-5):
+        h = O.hvp(g, m.c, m.rho, m.wavelet, obs, *v, rel_step=step)
+        assert rel_l2(h["hv_c"], ref["hv_c"]) <= 1e-8
+        assert rel_l2(h["hv_rho"], ref["hv_rho"]) <= 1e-8

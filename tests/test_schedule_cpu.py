@@ -76,3 +76,73 @@ def test_schedule(dump, T, K, S, Sa):
             i += 1
         adjoint((j + 1) * K, j * K + 1)
     assert i == len(seq)
+
+
+# ---------------------------------------------------------------- dispatch limits of the full benchmark plan
+
+GFX950_LDS_PER_WORKGROUP = 160 * 1024
+
+
+@pytest.mark.parametrize("spl", [2, 3])
+def test_uneven64_dispatch_parameters_within_limits(spl):
+    """Every launch of one gradient of the full 64-media benchmark workload
+    (two- and three-step schedules, 64 x 8 tiles, groups of 4, the
+    checkpointed plan under the box's 85 % budget), listed on the host by the
+    code that enqueues it: grids non-empty and below 2^32 work-items, the
+    256-lane step workgroups, dynamic LDS within gfx950's per-workgroup
+    limit, launch counts as the plan reports them, waves and steps in order."""
+    import paper_2603_04070_amd as F
+    import workloads as W
+    media = W.c4_batch(40, n_media=64)
+    grids = [F.GridSpec.of(m.geom, 1700.0) for m in media]
+    budget = 0.85 * 284 * 2 ** 30
+    plan = F.Plan(grids, dtype="f32", steps_per_launch=spl, rows=2, group=4, mem_budget=budget, host_only=True)
+    info = plan.info
+    L = plan.launches("execute")
+    steps = [l for l in L if l["step"] >= 0]
+    assert len(steps) == info["launches"]
+    assert info["steps_per_launch"] == spl
+    for l in L:
+        gx, gy = l["grid"]
+        assert gx >= 1 and gy >= 1 and gy <= 65535, l
+        assert gx * l["block"] < 2 ** 32, l
+        assert 0 <= l["lds_bytes"] <= GFX950_LDS_PER_WORKGROUP, l
+    for l in steps:
+        assert l["block"] == 256 and l["kernel"] in ("fwd1", "fwd2", "fwd3", "adj1", "adj2"), l
+        if l["kernel"] in ("fwd2", "fwd3", "adj2"):
+            assert l["lds_bytes"] > 0, l
+    order = [(l["wave"], l["step"]) for l in steps]
+    assert order == sorted(order)
+    # the grid of a launch never exceeds the blocks of its wave's items
+    assert max(l["grid"][0] for l in steps) <= sum(-(-g.nx // 64) * -(-g.nz // 8) * -(-g.n_tx // 4) for g in grids) * 2
+
+
+def test_host_only_plan_refuses_calls():
+    import numpy as np
+    import paper_2603_04070_amd as F
+    g = F.GridSpec(nx=64, nz=64, nt=50, h=1e-4, dt=2e-8, src=np.array([30 * 64 + 10], np.int32),
+                   rcv=np.array([[30 * 64 + 20]], np.int32), npml=20)
+    with pytest.raises(F.FwiError):
+        F.Plan([g], host_only=True)                 # no budget: nothing to size against
+    plan = F.Plan([g], host_only=True, mem_budget=1e9)
+    assert plan.workspace_bytes > 0 and len(plan.launches("forward")) > 0
+    with pytest.raises(F.FwiError) as e:
+        plan._call(F._lib().fwi_plan_execute, [{"c": None, "rho": None, "wavelet": None, "traces": None}],
+                   _FakeBuf(), _FakeStream())
+    assert e.value.status == 1 and "host-only" in str(e.value)
+
+
+class _FakeStream:
+    cuda_stream = 0
+
+
+class _FakeBuf:
+    """Stands in for a workspace tensor: the call is refused before it is used."""
+    def data_ptr(self):
+        return 0
+
+    def numel(self):
+        return 0
+
+    def element_size(self):
+        return 1
