@@ -195,6 +195,22 @@ fwi_status fwi_plan_forward(fwi_plan *plan, const fwi_io *io, void *workspace,
 fwi_status fwi_plan_adjoint(fwi_plan *plan, const fwi_io *io, void *workspace,
                             size_t workspace_bytes, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * computation as fwi_plan_execute, with the workspace taken from a static
+ * device array of FWI_SCRATCH_BYTES owned by the library (one per GPU, held
+ * until the process ends) instead of a caller's buffer.  The call allocates
+ * nothing (no hipMalloc, no graph: the plan's use_graph is ignored); the
+ * plan itself is created beforehand with fwi_plan_create.  io as for
+ * fwi_plan_execute.  FWI_ERR_WORKSPACE (nothing launched) when the plan's
+ * workspace size exceeds FWI_SCRATCH_BYTES: create such plans with
+ * mem_budget <= FWI_SCRATCH_BYTES so that the planner checkpoints or splits
+ * them into waves.  All calls on one GPU share the array, so calls that
+ * overlap in time on one GPU (two streams, two threads) race; serialise them.
+ * The call leaves no state that fwi_plan_adjoint could use. */
+#define FWI_SCRATCH_BYTES ((size_t)256 << 20)
+fwi_status fwi_plan_execute_scratch(fwi_plan *plan, const fwi_io *io, void *stream);
+
 /* Direction and outputs of fwi_plan_hvp for one medium (device pointers in
  * the plan's dtype, caller-owned, valid until the stream work completes). */
 typedef struct fwi_hvp_io {

@@ -207,6 +207,15 @@ class Plan:
         if st != _abi.FWI_OK:
             self._raise(st)
 
+    def execute_scratch(self, ios, stream=None):
+        """``execute`` with the library's static device scratch as workspace
+        (fwi_plan_execute_scratch: allocates nothing; plans up to
+        FWI_SCRATCH_BYTES of workspace; calls on one GPU must not overlap)."""
+        arr = self._ios(ios)
+        st = _lib().fwi_plan_execute_scratch(self._h, arr, _stream_handle(stream))
+        if st != _abi.FWI_OK:
+            self._raise(st)
+
     def forward(self, ios, workspace, stream=None):
         self._call(_lib().fwi_plan_forward, ios, workspace, stream)
 

@@ -18,8 +18,9 @@ EXPORTS = (
     "fwi_plan_create", "fwi_plan_workspace_size", "fwi_plan_get_info", "fwi_plan_execute",
     "fwi_plan_forward", "fwi_plan_adjoint", "fwi_plan_check", "fwi_plan_destroy",
     "fwi_status_string", "fwi_plan_last_error", "fwi_last_create_error", "fwi_autotune",
-    "fwi_plan_hvp", "fwi_plan_launches",
+    "fwi_plan_execute_scratch", "fwi_plan_hvp", "fwi_plan_launches",
 )
+FWI_SCRATCH_BYTES = 256 << 20
 
 
 class FwiGrid(C.Structure):
@@ -113,6 +114,8 @@ def load():
     lib.fwi_plan_launches.restype = C.c_int
     lib.fwi_plan_hvp.argtypes = [P, C.POINTER(FwiIO), C.POINTER(FwiHvpIO), P, C.c_size_t, P]
     lib.fwi_plan_hvp.restype = C.c_int
+    lib.fwi_plan_execute_scratch.argtypes = [P, C.POINTER(FwiIO), P]
+    lib.fwi_plan_execute_scratch.restype = C.c_int
     lib.fwi_plan_check.argtypes = [P]
     lib.fwi_plan_destroy.argtypes = [P]
     lib.fwi_plan_destroy.restype = None

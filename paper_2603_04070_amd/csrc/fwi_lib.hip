@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1467,6 +1468,63 @@ extern "C" fwi_status fwi_plan_hvp(fwi_plan* p, const fwi_io* io, const fwi_hvp_
                                    void* stream)
 {
     return run_call(p, io, ws, bytes, stream, kHvp, true, dir);
+}
+
+// ----------------------------------------------------------------------------- no-allocation variant
+//
+// The workspace of fwi_plan_execute_scratch lives in a file-scope device
+// array.  In host code its name stands for a host-side shadow, not a device
+// address: the device address is looked up once per device with
+// hipGetSymbolAddress (each GPU holds its own copy) and only that pointer is
+// handed to kernels.  Every call on a device shares the array; the launch
+// sequence clears what must start at zero (zero plane, accumulators, adjoint
+// planes) and writes everything else before reading it.
+
+static __device__ __align__(256) unsigned char scratch[FWI_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the scratch array on the current device (looked up once).
+fwi_status scratch_of_current_device(fwi_plan* p, void** out)
+{
+    int dev = -1;
+    HIPCHK(p, hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(p, FWI_ERR_INVALID, "device ordinal beyond the scratch table");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(p, FWI_ERR_HIP, std::string("hipGetSymbolAddress(scratch) failed: ") + hipGetErrorString(e));
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return FWI_OK;
+}
+
+}  // namespace
+
+extern "C" fwi_status fwi_plan_execute_scratch(fwi_plan* p, const fwi_io* io, void* stream)
+{
+    if (!p) return FWI_ERR_INVALID;
+    p->last_error.clear();
+    if (p->ws_bytes > FWI_SCRATCH_BYTES) {
+        char buf[256];
+        std::snprintf(buf, sizeof buf,
+                      "plan needs %zu bytes of workspace, the static scratch holds %zu: create the plan with a "
+                      "smaller mem_budget or fewer media",
+                      p->ws_bytes, (size_t)FWI_SCRATCH_BYTES);
+        return fail(p, FWI_ERR_WORKSPACE, buf);
+    }
+    void* ws = nullptr;
+    const fwi_status st = scratch_of_current_device(p, &ws);
+    if (st != FWI_OK) return st;
+    // the eager launch sequence only: recording a graph would allocate
+    return run_call(p, io, ws, FWI_SCRATCH_BYTES, stream, kExecute, /*allow_graph=*/false);
 }
 
 extern "C" fwi_status fwi_plan_launches(const fwi_plan* cp, int32_t call, fwi_launch* out, int64_t capacity,
