@@ -53,7 +53,8 @@ def parse():
     ap.add_argument("--tune", type=int, default=1, help="pick steps per launch and tile rows with the autotuner")
     ap.add_argument("--tune-cache", default="", help="JSON cache file of the autotuner")
     ap.add_argument("--mem-frac", type=float, default=0.85, help="workspace budget as a fraction of free HBM")
-    ap.add_argument("--plain-media", type=int, default=1, help="media of the workload timed in plain form (0: skip)")
+    ap.add_argument("--plain-media", type=int, default=64,
+                    help="media of the workload timed in plain form (0: skip; all of them by default)")
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--cpu-steps", type=int, default=0, help="oracle sample steps (0: sized for ~15 s)")
     ap.add_argument("--copy-calibration", type=int, default=0,
@@ -278,26 +279,36 @@ def main():
     if args.plain_media > 0 and args.mode == "batched":
         k = min(args.plain_media, len(media))
         sub, sub_dev, sub_obs = media[:k], mdev[:k], d_obs[:k]
+        progress(f"plain form on {k} media")
         pp = make_plan(sub, dtype, "plain", args, c_max)
-        pms, _ = time_gradient(pp, sub_dev, sub_obs, dtype, 1, 1, dev)
+        # one run: the plain form's launches are short and uniform, so a
+        # warm-up run changes nothing but the benchmark's length
+        pms, _ = time_gradient(pp, sub_dev, sub_obs, dtype, 1, 0, dev)
         pu = pp.info["cell_updates"]
         del pp
-        bp = make_plan(sub, dtype, "batched", args, c_max)
-        bms, _ = time_gradient(bp, sub_dev, sub_obs, dtype, 1, 1, dev)
-        del bp
+        if k == len(media):
+            bms = ms                     # the timed batched gradient of the same media
+        else:
+            bp = make_plan(sub, dtype, "batched", args, c_max)
+            bms, _ = time_gradient(bp, sub_dev, sub_obs, dtype, 1, 1, dev)
+            del bp
         torch.cuda.empty_cache()
         progress("plain form timed")
         plain = {"value": pu / (pms * 1e-3) / 1e9, "unit": "Gcell-updates/s", "media": k,
+                 "ms_per_gradient": round(pms, 1),
                  "batched_same_media": pu / (bms * 1e-3) / 1e9,
                  "speedup_batched_over_plain": pms / bms,
-                 "sample": f"first {k} medium(s) of the workload, {pu:.3e} cell-updates"}
+                 "sample": (f"{'all' if k == len(media) else 'first'} {k} medium(s) of the workload, "
+                            f"{pu:.3e} cell-updates, one run")}
 
     cpu = None
     if args.cpu_baseline:
+        import oracle
+        oracle.use_native()
         cpu = run_cpu_baseline(media, args)
-        # the same oracle on one core, on a sample sized for ~10 s
-        one = run_cpu_baseline(media, args, threads=1, seconds=10.0)
-        cpu["single_core"] = {k: one[k] for k in ("value", "cores", "seconds", "sample")}
+        # the same oracle on one core
+        one = run_cpu_baseline(media, args, threads=1, seconds=4.0)
+        cpu["single_core"] = {k: one[k] for k in ("value", "cores", "seconds", "runs_s", "sample")}
         progress("oracle baseline timed")
 
     # the committed counter runs measured the second-order kernels
@@ -352,16 +363,28 @@ def main():
     print(json.dumps(line))
 
 
-def run_cpu_baseline(media, args, threads=0, seconds=15.0):
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def run_cpu_baseline(media, args, threads=0, seconds=5.0, reps=3):
+    """The oracle (built for this host with -march=native) timed on a bounded
+    sample of the workload: one warm-up run, then the median of ``reps``."""
     import numpy as np
     import oracle
     m = media[0]
     g = m.geom
     if threads <= 0:
         threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or (os.cpu_count() or 1)
-    # ~`seconds` at the oracle's measured rate (~0.17 G updates/s on one core,
-    # ~0.28 on 16: it parallelises rows within a step): as many transmits as
-    # the full schedule allows, else the first steps of two
+    # ~`seconds` per run at the oracle's measured rate (~0.17 G updates/s on
+    # one core, ~0.28 on 16: it parallelises rows within a step): as many
+    # transmits as the full schedule allows, else the first steps of two
     budget_updates = seconds * (0.17e9 if threads == 1 else 0.28e9)
     ntx = int(min(g.n_tx, max(2, budget_updates // (2 * g.nx * g.nz * g.nt))))
     steps = args.cpu_steps
@@ -374,13 +397,19 @@ def run_cpu_baseline(media, args, threads=0, seconds=15.0):
     gs.nt = steps
     w = np.asarray(m.wavelet)[:ntx, :steps]
     d_obs = np.zeros((ntx, steps, gs.n_rcv))
-    t0 = time.perf_counter()
-    oracle.run(gs, m.c, m.rho, w, d_obs=d_obs, threads=threads)
-    sec = time.perf_counter() - t0
+    times = []
+    for r in range(1 + reps):
+        t0 = time.perf_counter()
+        oracle.run(gs, m.c, m.rho, w, d_obs=d_obs, threads=threads)
+        if r > 0:
+            times.append(time.perf_counter() - t0)
+    sec = float(np.median(times))
     upd = 2 * g.nx * g.nz * steps * ntx
     return {"value": round(upd / sec / 1e9, 4), "unit": "Gcell-updates/s", "cores": threads, "kind": "oracle",
-            "seconds": round(sec, 2),
-            "sample": f"medium 0 ({g.nx}x{g.nz}), {ntx} transmits, first {steps} steps, FP64, d_obs = 0"}
+            "seconds": round(sec, 2), "runs_s": [round(t, 2) for t in times], "warmup_runs": 1,
+            "cpu_model": cpu_model(), "nproc": os.cpu_count(), "build": "gcc -O3 -march=native -fopenmp",
+            "sample": (f"medium 0 ({g.nx}x{g.nz}), {ntx} transmits, first {steps} steps, FP64, d_obs = 0; "
+                       f"median of {reps} runs after one warm-up")}
 
 
 def load_traffic(info, launches, path=None):

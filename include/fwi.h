@@ -128,7 +128,10 @@ typedef struct fwi_options {
     int32_t host_only;       /* 1: plan on the host only, with no HIP call (mem_budget > 0       */
                              /*    required): sizes, info and fwi_plan_launches work, the calls  */
                              /*    return FWI_ERR_INVALID                                        */
-    int32_t reserved;
+    int32_t single_wave;     /* 1: keep every item resident at once (checkpointing as needed),   */
+                             /*    as fwi_plan_forward / fwi_plan_adjoint require; 0: with       */
+                             /*    ckpt_interval 0 the planner may instead keep every plane and  */
+                             /*    run the items in several waves when its cost model prefers it */
 } fwi_options;
 
 typedef struct fwi_plan fwi_plan;

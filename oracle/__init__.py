@@ -38,6 +38,23 @@ def build(force: bool = True) -> str:
     return _LIB_PATH
 
 
+_NATIVE_PATH = os.path.join(_HERE, "libfwi_oracle_native.so")
+
+
+def use_native() -> str:
+    """Rebuild the oracle for this host's own CPU (-march=native) and load that
+    build in place of the portable one: used only to time the oracle as a CPU
+    baseline on the machine it runs on."""
+    global _lib, _LIB_PATH
+    cmd = ["gcc", "-O3", "-march=native", "-fopenmp", "-fPIC", "-shared", "-Wall",
+           "-o", _NATIVE_PATH + ".tmp", _SRC, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(_NATIVE_PATH + ".tmp", _NATIVE_PATH)
+    _LIB_PATH = _NATIVE_PATH
+    _lib = None
+    return _LIB_PATH
+
+
 class _Medium(C.Structure):
     _fields_ = [
         ("nx", C.c_int32), ("nz", C.c_int32), ("nt", C.c_int32), ("npml", C.c_int32),

@@ -93,14 +93,16 @@ class Plan:
     differences, one step per launch).  ``hvp``: the plan serves
     ``hessian_vector`` (fwi_plan_hvp) only.  ``host_only``: plan on the host
     without any HIP call (needs ``mem_budget``): sizes, ``info`` and
-    ``launches`` only.
+    ``launches`` only.  ``single_wave``: keep every item resident at once
+    (needed by ``forward`` / ``adjoint``); otherwise an automatic ``ckpt``
+    lets the planner trade recompute for waves by its cost model.
     """
 
     def __init__(self, grids: Sequence[GridSpec], dtype: str = "f32", mode: str = "batched",
                  ckpt: int = 0, group: int = 0, rows: int = 0, use_graph: bool = False,
                  acc_double: bool = False, mem_budget: float = 0.0, steps_per_launch: int = 0,
                  forward_only: bool = False, persistent: bool = False, barrier_spin: int = 0, order: int = 2,
-                 hvp: bool = False, host_only: bool = False):
+                 hvp: bool = False, host_only: bool = False, single_wave: bool = False):
         lib = _lib()
         self.grids = list(grids)
         self.dtype = dtype
@@ -129,6 +131,7 @@ class Plan:
         opt.order = int(order)
         opt.hvp = int(bool(hvp))
         opt.host_only = int(bool(host_only))
+        opt.single_wave = int(bool(single_wave))
         self.order = int(order)
         self.hvp_plan = bool(hvp)
         self._h = C.c_void_p()

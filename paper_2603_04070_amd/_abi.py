@@ -51,7 +51,7 @@ class FwiOptions(C.Structure):
         ("mem_budget", C.c_double),
         ("tune_cache", C.c_char_p),
         ("order", C.c_int32), ("hvp", C.c_int32),
-        ("host_only", C.c_int32), ("reserved", C.c_int32),
+        ("host_only", C.c_int32), ("single_wave", C.c_int32),
     ]
 
 

@@ -73,6 +73,8 @@ class WavePhysics(torch.nn.Module):
     def __init__(self, grids: Sequence[GridSpec], dtype: str = "f32", **plan_options):
         super().__init__()
         plan_options.setdefault("mode", "batched")
+        # the split forward / adjoint calls need every item resident at once
+        plan_options.setdefault("single_wave", True)
         self.plan = Plan(list(grids), dtype=dtype, **plan_options)
 
     def forward(self, c, rho, wavelet):

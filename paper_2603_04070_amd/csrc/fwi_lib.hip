@@ -530,6 +530,7 @@ static fwi_status create_impl(fwi_plan* p, fwi_dtype dtype, const fwi_grid* grid
     if (o.order != 0 && o.order != 2 && o.order != 4) return fail(p, FWI_ERR_INVALID, "order must be 0, 2 or 4");
     if (o.hvp != 0 && o.hvp != 1) return fail(p, FWI_ERR_INVALID, "hvp must be 0 or 1");
     if (o.host_only != 0 && o.host_only != 1) return fail(p, FWI_ERR_INVALID, "host_only must be 0 or 1");
+    if (o.single_wave != 0 && o.single_wave != 1) return fail(p, FWI_ERR_INVALID, "single_wave must be 0 or 1");
     if (o.hvp && (o.order == 4 || o.persistent || o.use_graph || o.forward_only || o.steps_per_launch > 1))
         return fail(p, FWI_ERR_INVALID, "hvp plans run the second-order operator one step per launch, "
                                         "not persistent, without graph, not forward-only");
@@ -691,9 +692,44 @@ static fwi_status create_impl(fwi_plan* p, fwi_dtype dtype, const fwi_grid* grid
         }
         for (int i = 0; i < n_items; ++i) p->waves.push_back(Wave{{i}});
     } else {
-        double total = 0;
-        for (auto& it : p->items) total += (double)state_bytes(it, it.K);
-        if (total <= state_budget) {
+        // Replay strategies: (a) K ~ sqrt(2T) for every item, all items resident
+        // together when they fit (one wave), items upgraded to store-all
+        // smallest first while the budget allows, else waves; (b) every plane
+        // kept (no recompute), items packed into as many waves as the budget
+        // needs; (c) two segments per item (half the planes, half a forward
+        // recomputed), in waves.  With an automatic interval the planner keeps
+        // the one its cost model prices lowest (executed cell-updates plus a
+        // fixed cost per launch); a given interval takes (a)'s packing.
+        auto pack = [&]() {
+            // waves of items with similar schedule length, each within the budget
+            std::vector<Wave> waves;
+            std::vector<int> order(n_items);
+            for (int i = 0; i < n_items; ++i) order[i] = i;
+            auto steps_of = [&](int i) {
+                const ItemPlan& it = p->items[i];
+                const int T = p->media[it.medium].g.nt, J = (T + it.K - 1) / it.K;
+                return 2 * T + it.K * (J - 1);
+            };
+            std::stable_sort(order.begin(), order.end(), [&](int a2, int b2) { return steps_of(a2) > steps_of(b2); });
+            Wave w;
+            double used = 0;
+            for (int i : order) {
+                const double sb = (double)state_bytes(p->items[i], p->items[i].K);
+                if (!w.items.empty() && used + sb > state_budget) {
+                    waves.push_back(w);
+                    w = Wave{};
+                    used = 0;
+                }
+                w.items.push_back(i);
+                used += sb;
+            }
+            if (!w.items.empty()) waves.push_back(w);
+            return waves;
+        };
+        auto strategy_a = [&]() {
+            double total = 0;
+            for (auto& it : p->items) total += (double)state_bytes(it, it.K);
+            if (total > state_budget) return pack();
             if (o.ckpt_interval == 0) {
                 // one wave: keep every plane for as many items as the budget allows
                 std::vector<int> order(n_items);
@@ -711,31 +747,73 @@ static fwi_status create_impl(fwi_plan* p, fwi_dtype dtype, const fwi_grid* grid
             }
             Wave w;
             for (int i = 0; i < n_items; ++i) w.items.push_back(i);
-            p->waves.push_back(w);
-        } else {
-            // waves of items with similar schedule length, each within the budget
-            std::vector<int> order(n_items);
-            for (int i = 0; i < n_items; ++i) order[i] = i;
-            auto steps_of = [&](int i) {
-                const ItemPlan& it = p->items[i];
-                const int T = p->media[it.medium].g.nt, J = (T + it.K - 1) / it.K;
-                return 2 * T + it.K * (J - 1);
-            };
-            std::stable_sort(order.begin(), order.end(), [&](int a2, int b2) { return steps_of(a2) > steps_of(b2); });
-            Wave w;
-            double used = 0;
-            for (int i : order) {
-                const double sb = (double)state_bytes(p->items[i], p->items[i].K);
-                if (!w.items.empty() && used + sb > state_budget) {
-                    p->waves.push_back(w);
-                    w = Wave{};
-                    used = 0;
-                }
-                w.items.push_back(i);
-                used += sb;
+            return std::vector<Wave>{w};
+        };
+        // modelled seconds of one gradient: executed cell-updates (recompute
+        // included) at the step kernels' rate plus a fixed cost per launch
+        // (MI355X, FP32, groups of 4, three forward steps per launch: 2.26 ps
+        // per executed update and 10 us per launch reproduce both the
+        // one-wave checkpointed and the 22-wave store-all timing of the
+        // 64-media benchmark workload; FP64 updates cost twice as much)
+        auto model_seconds = [&](const std::vector<Wave>& waves) {
+            const double t_update = 2.26e-12 * (dtype == FWI_F64 ? 2.0 : 1.0), t_launch = 10e-6;
+            int S = p->S;
+            for (auto& it : p->items)
+                if (S >= 2 && it.K < 4 && it.K < p->media[it.medium].g.nt) S = 1;
+            const int Sa = std::min(S, 2);
+            double exec = 0, launches = 0;
+            for (auto& it : p->items) {
+                const MediumPlan& m = p->media[it.medium];
+                const int T = m.g.nt, J = (T + it.K - 1) / it.K;
+                exec += (double)m.g.nx * m.g.nz * it.g_used * (2.0 * T + (double)it.K * (J - 1));
             }
-            if (!w.items.empty()) p->waves.push_back(w);
+            for (const Wave& w : waves) {
+                int steps = 0;
+                for (int i : w.items) {
+                    const ItemPlan& it = p->items[i];
+                    const int T = p->media[it.medium].g.nt, J = (T + it.K - 1) / it.K, last = T - (J - 1) * it.K;
+                    steps = std::max(steps, (T + S - 1) / S + (last + Sa - 1) / Sa +
+                                                ((it.K + S - 1) / S + (it.K + Sa - 1) / Sa) * (J - 1));
+                }
+                for (int s2 = 0; s2 < steps; ++s2) {
+                    unsigned bits = 0;
+                    for (int i : w.items) {
+                        const ItemPlan& it = p->items[i];
+                        const int T = p->media[it.medium].g.nt;
+                        const Step st = decode(T, it.K, (T + it.K - 1) / it.K, s2, S, Sa);
+                        if (st.phase == kIdle) continue;
+                        bits |= st.phase == kAdj ? (st.count == 2 ? 8u : 4u)
+                                                 : (st.count == 3 ? 16u : st.count == 2 ? 2u : 1u);
+                    }
+                    launches += __builtin_popcount(bits);
+                }
+            }
+            return exec * t_update + launches * t_launch;
+        };
+        std::vector<Wave> best = strategy_a();
+        if (o.ckpt_interval == 0 && !o.forward_only && !o.single_wave) {
+            std::vector<int> best_k(n_items);
+            for (int i = 0; i < n_items; ++i) best_k[i] = p->items[i].K;
+            double best_t = model_seconds(best);
+            for (int variant = 0; variant < 2; ++variant) {
+                for (auto& it : p->items) {
+                    const int T = p->media[it.medium].g.nt;
+                    int K = variant == 0 ? T : (T + 1) / 2;
+                    if (variant == 1 && p->S == 3 && K % 6 && K < T) K += 6 - K % 6;
+                    if (variant == 1 && p->S == 2 && K % 2 && K < T) ++K;
+                    it.K = std::max(1, std::min(K, T));
+                }
+                std::vector<Wave> cand = pack();
+                const double t = model_seconds(cand);
+                if (t < best_t) {
+                    best_t = t;
+                    best = cand;
+                    for (int i = 0; i < n_items; ++i) best_k[i] = p->items[i].K;
+                }
+            }
+            for (int i = 0; i < n_items; ++i) p->items[i].K = best_k[i];
         }
+        p->waves = best;
     }
     // a launch of two or three steps reads and writes up to four field planes
     // of the segment buffer at once: that needs K >= 4 wherever the buffer wraps
@@ -1395,8 +1473,8 @@ fwi_status run_call(fwi_plan* p, const fwi_io* io, void* workspace, size_t bytes
     if (call == kAdjoint && std::find(p->fwd_ws.begin(), p->fwd_ws.end(), workspace) == p->fwd_ws.end())
         return fail(p, FWI_ERR_STATE, "no forward state in this workspace");
     if (call != kExecute && call != kHvp && p->waves.size() > 1)
-        return fail(p, FWI_ERR_INVALID, "forward/adjoint need every item resident at once: use FWI_BATCHED "
-                                        "with a memory budget that holds all items");
+        return fail(p, FWI_ERR_INVALID, "forward/adjoint need every item resident at once: create the plan "
+                                        "with single_wave = 1 and a memory budget that holds all items");
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     unsigned char* ws = reinterpret_cast<unsigned char*>(workspace);
 

@@ -26,9 +26,12 @@ def subset(medium, tx):
 
 
 def oracle_obs(medium_obs, threads=0, ckpt=0):
+    """Observed traces: the oracle's forward solve of ``medium_obs``, rounded
+    to FP32 once, so that both sides are fed the same observed data."""
     import oracle
     g = medium_obs.geom
-    return oracle.run(g, medium_obs.c, medium_obs.rho, medium_obs.wavelet, ckpt=ckpt, threads=threads)["traces"]
+    tr = oracle.run(g, medium_obs.c, medium_obs.rho, medium_obs.wavelet, ckpt=ckpt, threads=threads)["traces"]
+    return tr.astype(np.float32)
 
 
 def oracle_grad(medium, d_obs, threads=0, ckpt=0):
@@ -48,6 +51,8 @@ def gpu_run(media, d_obs_list, dtype="f32", c_max=None, d_adj_list=None, split=F
     for m in media:
         cm = float(c_max) if c_max is not None else float(np.max(m.c)) * 1.0001
         grids.append(F.GridSpec.of(m.geom, cm))
+    if split or d_adj_list is not None:
+        plan_kw.setdefault("single_wave", True)       # split calls keep every item resident
     plan = F.Plan(grids, dtype=dtype, **plan_kw)
     dev = torch.device("cuda:0")
     ios, outs = [], []

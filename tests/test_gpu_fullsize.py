@@ -1,8 +1,9 @@
 """The benchmark workload at full size, in the launch configuration bench.py
 times (64 uneven media in one batched plan, three forward and two adjoint
-steps per launch, 64 x 8 tiles, groups of 4 transmits, checkpointed replay
-under an 85 % memory budget), checked on outputs the oracle computes in a
-minute: the medium with the fewest cell-updates (traces, misfit, gradient
+steps per launch, 64 x 8 tiles, groups of 4 transmits, an 85 % memory
+budget and the planner's automatic replay choice: every plane kept, items in
+waves) and in the one-wave checkpointed configuration, checked on outputs
+the oracle computes in a minute: the medium with the fewest cell-updates (traces, misfit, gradient
 over all its transmits), and the largest medium (768-class grid, longest
 schedule) with its first and last transmits driven by the Ricker pulse and
 observed data, its other transmits by a zero wavelet and zero observed data
@@ -41,12 +42,29 @@ def test_uneven64_full_size_sampled():
     obs_big[tx] = obs_big2
     c_max = 1.02 * max(float(np.max(m.c)) for m in media + [partner, partner_big])
     grids = [F.GridSpec.of(m.geom, c_max) for m in media]
-    torch.cuda.empty_cache()
-    free, _ = torch.cuda.mem_get_info()
-    plan = F.Plan(grids, dtype="f32", steps_per_launch=3, rows=2, group=4, mem_budget=0.85 * free)
-    info = plan.info
-    assert info["steps_per_launch"] == 3 and info["recompute_updates"] > 0
     dev = torch.device("cuda:0")
+    print(f"[fullsize] oracle: gradient of medium {big}, transmits {tx}", flush=True)
+    rb = oracle_grad(subset(mb, tx), obs_big2, ckpt=100)
+    r = oracle_grad(media[small], obs_small)
+    for single_wave in (False, True):
+        torch.cuda.empty_cache()
+        free, _ = torch.cuda.mem_get_info()
+        plan = F.Plan(grids, dtype="f32", steps_per_launch=3, rows=2, group=4, mem_budget=0.85 * free,
+                      single_wave=single_wave)
+        info = plan.info
+        assert info["steps_per_launch"] == 3
+        if single_wave:
+            assert info["waves"] == 1 and info["recompute_updates"] > 0
+        else:
+            assert info["waves"] > 1 and info["recompute_updates"] == 0
+        _run_and_check(plan, grids, media, small, big, tx, keep, obs_small, obs_big, rb, r, dev)
+        del plan
+        torch.cuda.empty_cache()
+
+
+def _run_and_check(plan, grids, media, small, big, tx, keep, obs_small, obs_big, rb, r, dev):
+    import torch
+    info = plan.info
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float32)).to(dev)
     ios = []
     for i, (g, m) in enumerate(zip(grids, media)):
@@ -63,15 +81,12 @@ def test_uneven64_full_size_sampled():
     print(f"plan: waves {info['waves']}, K {info['min_ckpt']}..{info['max_ckpt']}, "
           f"launches {info['launches']}; checked media: small {small} {media[small].name}, big {big} {media[big].name}")
     # the largest medium: the two driven transmits' traces, misfit and gradient
-    print(f"[fullsize] oracle: gradient of medium {big}, transmits {tx}", flush=True)
-    rb = oracle_grad(subset(mb, tx), obs_big2, ckpt=100)
     got = ios[big]["traces"].cpu().numpy()
     assert np.all(got[~keep] == 0.0)
     eb = {k: rel_l2(ios[big][k].cpu().numpy(), rb[k]) for k in ("grad_c", "grad_rho")}
     eb["traces"] = rel_l2(got[tx], rb["traces"])
     eb["misfit"] = abs(float(ios[big]["misfit"]) - rb["misfit"]) / rb["misfit"]
     # the smallest medium: traces, misfit, gradients
-    r = oracle_grad(media[small], obs_small)
     e = {k: rel_l2(ios[small][k].cpu().numpy(), r[k]) for k in ("traces", "grad_c", "grad_rho")}
     e["misfit"] = abs(float(ios[small]["misfit"]) - r["misfit"]) / r["misfit"]
     print("largest medium", eb, "smallest medium", e, flush=True)
