@@ -71,6 +71,7 @@ class _Medium(C.Structure):
         ("misfit", C.c_void_p),
         ("fields", C.c_void_p),
         ("order", C.c_int32), ("pad", C.c_int32),
+        ("eta", C.c_void_p), ("grad_eta", C.c_void_p),
     ]
 
 
@@ -82,7 +83,7 @@ def _load():
         lib = C.CDLL(_LIB_PATH)
         lib.om_run.argtypes = [C.POINTER(_Medium), C.c_int, C.c_int]
         lib.om_run.restype = C.c_int
-        lib.om_born.argtypes = [C.POINTER(_Medium), C.c_void_p, C.c_void_p, C.c_void_p]
+        lib.om_born.argtypes = [C.POINTER(_Medium), C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
         lib.om_born.restype = C.c_int
         lib.om_dmax.argtypes = [C.c_double, C.c_double, C.c_int, C.c_double]
         lib.om_dmax.restype = C.c_double
@@ -113,7 +114,7 @@ def damping(nx: int, nz: int, N: int, dm: float) -> np.ndarray:
     return out
 
 
-def _medium_struct(geom, c, rho, wavelet, keep):
+def _medium_struct(geom, c, rho, wavelet, keep, eta=None):
     c = _f64(c); rho = _f64(rho)
     w = _f64(wavelet)
     if w.ndim == 1:
@@ -130,12 +131,16 @@ def _medium_struct(geom, c, rho, wavelet, keep):
     m.src, m.rcv = _ptr(src), _ptr(rcv)
     m.wavelet, m.wavelet_stride = _ptr(w), stride
     m.order = int(getattr(geom, "order", 2))
+    if eta is not None:
+        eta = _f64(eta)
+        keep.append(eta)
+        m.eta = _ptr(eta)
     return m
 
 
 def run(geom, c, rho, wavelet, d_obs=None, d_adj=None, gradient: Optional[bool] = None,
         ckpt: int = 0, threads: int = 0, want_fields: bool = False,
-        want_kappa_b: bool = False, want_wavelet_grad: bool = False) -> dict:
+        want_kappa_b: bool = False, want_wavelet_grad: bool = False, eta=None) -> dict:
     """Forward traces, misfit and (when d_obs or d_adj is given) the gradient.
 
     Returns a dict with ``traces`` [n_tx, nt, n_rcv] and, as requested,
@@ -144,7 +149,7 @@ def run(geom, c, rho, wavelet, d_obs=None, d_adj=None, gradient: Optional[bool] 
     ``ckpt`` is the checkpoint interval K (0 = keep every forward plane).
     """
     keep = []
-    m = _medium_struct(geom, c, rho, wavelet, keep)
+    m = _medium_struct(geom, c, rho, wavelet, keep, eta)
     P, T, R, n = geom.n_tx, geom.nt, geom.n_rcv, geom.nx * geom.nz
     out = {"traces": np.zeros((P, T, R), np.float64)}
     m.traces = _ptr(out["traces"])
@@ -161,6 +166,8 @@ def run(geom, c, rho, wavelet, d_obs=None, d_adj=None, gradient: Optional[bool] 
         if want_kappa_b:
             out["grad_kappa"] = np.zeros((geom.nz, geom.nx)); m.grad_kappa = _ptr(out["grad_kappa"])
             out["grad_b"] = np.zeros((geom.nz, geom.nx)); m.grad_b = _ptr(out["grad_b"])
+        if eta is not None:
+            out["grad_eta"] = np.zeros((geom.nz, geom.nx)); m.grad_eta = _ptr(out["grad_eta"])
         if want_wavelet_grad:
             out["grad_wavelet"] = np.zeros((P, T)); m.grad_wavelet = _ptr(out["grad_wavelet"])
     if want_fields:
@@ -193,13 +200,14 @@ def apply_lb(c, rho, h: float, v, order: int = 2) -> np.ndarray:
     return out
 
 
-def born(geom, c, rho, wavelet, dc, drho) -> np.ndarray:
-    """Tangent-linear traces J (dc, drho), [n_tx, nt, n_rcv] (test-only)."""
+def born(geom, c, rho, wavelet, dc, drho, eta=None, deta=None) -> np.ndarray:
+    """Tangent-linear traces J (dc, drho[, deta]), [n_tx, nt, n_rcv] (test-only)."""
     keep = []
-    m = _medium_struct(geom, c, rho, wavelet, keep)
+    m = _medium_struct(geom, c, rho, wavelet, keep, eta)
     dc = _f64(dc); drho = _f64(drho)
+    de = None if deta is None else _f64(deta)
     out = np.zeros((geom.n_tx, geom.nt, geom.n_rcv))
-    rc = _load().om_born(C.byref(m), _ptr(dc), _ptr(drho), _ptr(out))
+    rc = _load().om_born(C.byref(m), _ptr(dc), _ptr(drho), None if de is None else _ptr(de), _ptr(out))
     if rc != 0:
         raise RuntimeError(f"oracle om_born failed with status {rc}")
     return out

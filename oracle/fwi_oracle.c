@@ -48,6 +48,17 @@
  *    G_f = -h^-2 (D u)_f (D w)_f, shared half and half by the cells whose b
  *    make up b_f (ghost cells counting as the cell they repeat).
  *
+ * Attenuation (the Sec. VII extension of the forward model): a per-cell
+ *    damping rate eta(x) >= 0 (1/s) is added to eq. 1's damping term, so that
+ *    D becomes D + eta everywhere in the coefficients above (eq. 2's a and
+ *    beta discretise u_tt + 2 D u_t + D^2 u, so in a homogeneous medium the
+ *    loss-free response is multiplied by exp(-eta t) in the continuum).  Its
+ *    gradient follows from the update's dependence on e = (D + eta) dt:
+ *      dJ/deta(x) = dt sum_{t=1..T} lam^t_x ( a'(e) u^{t-1}_x + beta'(e) u^{t-2}_x
+ *                                            + gamma'(e) kappa_x (L_b u^{t-1})_x ),
+ *      a' = -(e^2 + 2e + 2)/(1+e)^2, beta' = 2/(1+e)^2, gamma' = -dt^2/(1+e)^2,
+ *    with lam^t the adjoint of the update that produced u^t (above).
+ *
  * Replay of u^{t-1} in reverse order: every u^t is kept (store-all), or
  * (u^{jK}, u^{jK-1}) pairs are kept every K steps and each segment is
  * recomputed with the same step routine (bitwise identical to store-all).
@@ -79,6 +90,8 @@ typedef struct {
     double *fields;                 /* out: forward fields u^1..u^T of transmit 0, [nt][nz*nx], or NULL */
     int32_t order;                  /* spatial order of L_b: 2 (default when 0) or 4 */
     int32_t pad;
+    const double *eta;              /* [nz*nx] attenuation rate (1/s), or NULL (= 0) */
+    double *grad_eta;               /* out [nz*nx] dJ/deta, or NULL */
 } om_medium;
 
 enum { OM_OK = 0, OM_ERR_INVALID = 1, OM_ERR_NOMEM = 4 };
@@ -117,11 +130,13 @@ typedef struct {
     int nthr;                       /* OpenMP threads of the row loops */
     double ih2;                     /* h^-2 */
     double *a, *beta, *gam, *kap, *b, *gk;   /* gk = gamma * kappa */
+    double *da, *dbeta, *dgam;      /* derivatives of a, beta, gamma with respect to e = D dt */
 } om_coef;
 
 static void coef_free(om_coef *k)
 {
     free(k->a); free(k->beta); free(k->gam); free(k->kap); free(k->b); free(k->gk);
+    free(k->da); free(k->dbeta); free(k->dgam);
 }
 
 static int coef_make(const om_medium *m, om_coef *k)
@@ -133,17 +148,25 @@ static int coef_make(const om_medium *m, om_coef *k)
     k->a = malloc(sizeof(double) * n); k->beta = malloc(sizeof(double) * n);
     k->gam = malloc(sizeof(double) * n); k->kap = malloc(sizeof(double) * n);
     k->b = malloc(sizeof(double) * n); k->gk = malloc(sizeof(double) * n);
-    if (!k->a || !k->beta || !k->gam || !k->kap || !k->b || !k->gk) { coef_free(k); return OM_ERR_NOMEM; }
+    k->da = malloc(sizeof(double) * n); k->dbeta = malloc(sizeof(double) * n); k->dgam = malloc(sizeof(double) * n);
+    if (!k->a || !k->beta || !k->gam || !k->kap || !k->b || !k->gk || !k->da || !k->dbeta || !k->dgam) {
+        coef_free(k);
+        return OM_ERR_NOMEM;
+    }
     double dmax = om_dmax(m->pml_cref, m->pml_r, m->npml, m->h);
     double dt = m->dt;
     for (int iz = 0; iz < m->nz; ++iz)
         for (int ix = 0; ix < m->nx; ++ix) {
             int x = iz * m->nx + ix;
             double D = om_prof(ix, m->nx, m->npml, dmax) + om_prof(iz, m->nz, m->npml, dmax);
-            double den = 1.0 + D * dt;
-            k->a[x] = (2.0 - D * D * dt * dt) / den;
-            k->beta[x] = (D * dt - 1.0) / den;
+            if (m->eta) D += m->eta[x];
+            double e = D * dt, den = 1.0 + e;
+            k->a[x] = (2.0 - e * e) / den;
+            k->beta[x] = (e - 1.0) / den;
             k->gam[x] = dt * dt / den;
+            k->da[x] = -(e * e + 2.0 * e + 2.0) / (den * den);
+            k->dbeta[x] = 2.0 / (den * den);
+            k->dgam[x] = -dt * dt / (den * den);
             k->kap[x] = m->rho[x] * m->c[x] * m->c[x];
             k->b[x] = 1.0 / m->rho[x];
             k->gk[x] = k->gam[x] * k->kap[x];
@@ -305,6 +328,17 @@ static void imaging(const om_coef *k, const double *lam, const double *u, double
         }
 }
 
+/* Attenuation term of the gradient at one adjoint time t:
+ * ge(x) += lam^t_x (a' u^{t-1} + beta' u^{t-2} + gamma' kappa L_b u^{t-1})_x, derivatives in e. */
+static void att_imaging(const om_coef *k, const double *lam, const double *u1, const double *u2, double *ge)
+{
+    for (int iz = 0; iz < k->nz; ++iz)
+        for (int ix = 0; ix < k->nx; ++ix) {
+            int x = iz * k->nx + ix;
+            ge[x] += lam[x] * (k->da[x] * u1[x] + k->dbeta[x] * u2[x] + k->dgam[x] * k->kap[x] * lb_at(k, u1, ix, iz));
+        }
+}
+
 /* ---------------------------------------------------------------- one transmit */
 
 typedef struct {
@@ -315,6 +349,7 @@ typedef struct {
     int par;                        /* parallelise rows */
     double *traces;                 /* [nt][n_rcv] for this transmit */
     double *gkap, *gb;              /* [n] per-transmit accumulators */
+    double *ge;                     /* [n] dJ/de accumulator, or NULL */
     double *gw;                     /* [nt] or NULL */
     double J;
 } om_tx;
@@ -353,7 +388,7 @@ static int run_transmit(om_tx *t)
     int K = t->K < 1 ? 1 : t->K;
     if (K > T) K = T;
     int want_adj = (m->d_obs || m->d_adj) &&
-                   (m->grad_c || m->grad_rho || m->grad_kappa || m->grad_b || m->grad_wavelet);
+                   (m->grad_c || m->grad_rho || m->grad_kappa || m->grad_b || m->grad_wavelet || m->grad_eta);
     if (!want_adj && m->fields) K = T;             /* keep every plane to hand them out */
     int J = (T + K - 1) / K;                       /* segments */
 
@@ -420,6 +455,14 @@ static int run_transmit(om_tx *t)
                                    : (tt - 1 == n0) ? ck + (size_t)(2 * j + 1) * n
                                    : seg + (size_t)(tt - 2 - n0) * n;
                 imaging(k, l0, um1, w, t->gkap, t->gb, t->par);
+                if (t->ge) {
+                    /* u^{t-2}: checkpoint pair (u^{n0-1}, u^{n0}) at the segment start, zero before u^1 */
+                    const double *um2 = (tt - 2 <= 0) ? zero
+                                       : (tt - 2 == n0) ? ck + (size_t)(2 * j + 1) * n
+                                       : (tt - 2 == n0 - 1) ? ck + (size_t)(2 * j) * n
+                                       : seg + (size_t)(tt - 3 - n0) * n;
+                    att_imaging(k, l0, um1, um2, t->ge);
+                }
                 double *tmp = l2; l2 = l1; l1 = l0; l0 = tmp;
             }
         }
@@ -439,6 +482,9 @@ static int valid(const om_medium *m)
     if (m->wavelet_stride != 0 && m->wavelet_stride < m->nt) return 0;
     if (m->order != 0 && m->order != 2 && m->order != 4) return 0;
     int n = m->nx * m->nz;
+    if (m->eta)
+        for (int x = 0; x < n; ++x)
+            if (!(m->eta[x] >= 0.0) || !isfinite(m->eta[x])) return 0;
     for (int p = 0; p < m->n_tx; ++p) {
         if (m->src[p] < 0 || m->src[p] >= n) return 0;
         for (int r = 0; r < m->n_rcv; ++r)
@@ -468,7 +514,11 @@ int om_run(om_medium *m, int ckpt, int threads)
     double *gk = calloc((size_t)P * n, sizeof(double));
     double *gb = calloc((size_t)P * n, sizeof(double));
     double *Jp = calloc((size_t)P, sizeof(double));
-    if (!tr || !gk || !gb || !Jp) { coef_free(&k); free(gk); free(gb); free(Jp); if (!m->traces) free(tr); return OM_ERR_NOMEM; }
+    double *ge = m->grad_eta ? calloc((size_t)P * n, sizeof(double)) : NULL;
+    if (!tr || !gk || !gb || !Jp || (m->grad_eta && !ge)) {
+        coef_free(&k); free(gk); free(gb); free(Jp); free(ge); if (!m->traces) free(tr);
+        return OM_ERR_NOMEM;
+    }
 
     int over_tx = P >= nthr && nthr > 1;
     int rc = OM_OK;
@@ -479,6 +529,7 @@ int om_run(om_medium *m, int ckpt, int threads)
         t.m = m; t.k = &k; t.p = p; t.K = K; t.par = !over_tx;
         t.traces = tr + (size_t)p * T * nr;
         t.gkap = gk + (size_t)p * n; t.gb = gb + (size_t)p * n;
+        t.ge = ge ? ge + (size_t)p * n : NULL;
         t.gw = m->grad_wavelet ? m->grad_wavelet + (size_t)p * T : NULL;
         int r = run_transmit(&t);
         Jp[p] = t.J;
@@ -498,10 +549,15 @@ int om_run(om_medium *m, int ckpt, int threads)
             if (m->grad_b) m->grad_b[x] = sb;
             if (m->grad_c) m->grad_c[x] = 2.0 * rho * c * sk;
             if (m->grad_rho) m->grad_rho[x] = c * c * sk - b * b * sb;
+            if (m->grad_eta) {
+                double se = 0.0;
+                for (int p = 0; p < P; ++p) se += ge[(size_t)p * n + x];
+                m->grad_eta[x] = m->dt * se;
+            }
         }
     }
     coef_free(&k);
-    free(gk); free(gb); free(Jp);
+    free(gk); free(gb); free(Jp); free(ge);
     if (!m->traces) free(tr);
     return rc;
 }
@@ -510,8 +566,10 @@ int om_run(om_medium *m, int ckpt, int threads)
  *   du^{n+1} = a du^n + beta du^{n-1} + gamma kappa L_b du^n
  *            + gamma dkappa L_b u^n + gamma kappa L_db u^n,
  *   dkappa = 2 rho c dc + c^2 drho, db = -drho / rho^2, db_f averaged like b_f;
+ *   with deta (may be NULL) also + de (a' u^n + beta' u^{n-1} + gamma' kappa L_b u^n),
+ *   de = deta dt;
  *   dd_p[n][r] = du^{n+1}[rcv_{p,r}]. */
-int om_born(om_medium *m, const double *dc, const double *drho, double *dtraces)
+int om_born(om_medium *m, const double *dc, const double *drho, const double *deta, double *dtraces)
 {
     if (!valid(m) || !dc || !drho || !dtraces) return OM_ERR_INVALID;
     int nx = m->nx, nz = m->nz, n = nx * nz, T = m->nt, nr = m->n_rcv;
@@ -537,6 +595,10 @@ int om_born(om_medium *m, const double *dc, const double *drho, double *dtraces)
                     dn[x] = k.a[x] * dcu[x] + k.beta[x] * dp[x] + k.gk[x] * lb_at(&k, dcu, ix, iz)
                           + k.gam[x] * dkap[x] * lb_at(&k, uc, ix, iz)
                           + k.gk[x] * lb_at(&kd, uc, ix, iz);
+                    if (deta) {
+                        double de = deta[x] * m->dt;   /* perturbation of e = (D + eta) dt */
+                        dn[x] += de * (k.da[x] * uc[x] + k.dbeta[x] * up[x] + k.dgam[x] * k.kap[x] * lb_at(&k, uc, ix, iz));
+                    }
                 }
             fwd_step(&k, up, uc, un, 0);
             un[m->src[p]] += wav(m, p, s);

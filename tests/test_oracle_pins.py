@@ -24,6 +24,10 @@ Each test names what it pins:
       Laplacians (constant and variable density)
   P17 fourth-order variant: Green's function, dot products, brute-force
       gradient, density-scale invariance, checkpoint replay, stability bound
+  P19 attenuation (a damping rate eta(x) added to eq. 1's damping term): an
+      exact modal solution of the discrete update for a homogeneous medium
+      with uniform eta, brute-force gradient in eta, dot product of the
+      tangent-linear model with the adjoint, eta = 0 bitwise the loss-free run
   P18 Hessian-vector product (differences of oracle gradients): at zero
       residual it is 2 J^T J v (tangent-linear traces fed back through the
       adjoint), it is symmetric, v^T H v is the second derivative of the
@@ -574,3 +578,93 @@ def test_p18_hvp_step_plateau():
         h = O.hvp(g, m.c, m.rho, m.wavelet, obs, *v, rel_step=step)
         assert rel_l2(h["hv_c"], ref["hv_c"]) <= 1e-8
         assert rel_l2(h["hv_rho"], ref["hv_rho"]) <= 1e-8
+
+
+# ---------------------------------------------------------------- P19 attenuation
+
+def _modal_traces(nx, nz, nt, h, dt, c, rho, eta, src, rcv, w):
+    """Traces of the update of eq. 2 with damping e = eta dt (uniform), no
+    absorbing layer, constant c and rho, zero field outside the grid, by
+    its exact modal decomposition: the 5-point operator with zero ghosts has
+    the separable sine eigenvectors phi_kl(ix, iz) = sin(pi k (ix+1)/(nx+1))
+    sin(pi l (iz+1)/(nz+1)) with eigenvalue -(4/h^2)(sin^2(pi k/(2(nx+1)))
+    + sin^2(pi l/(2(nz+1)))) / rho, so each mode amplitude follows the scalar
+    recurrence A^{n+1} = (a + gamma kappa mu) A^n + beta A^{n-1} + w[n] phi(src) / |phi|^2."""
+    k = np.arange(1, nx + 1)[:, None]
+    l = np.arange(1, nz + 1)[None, :]
+    mu = -(4.0 / (h * h * rho)) * (np.sin(np.pi * k / (2 * (nx + 1))) ** 2 + np.sin(np.pi * l / (2 * (nz + 1))) ** 2)
+    e = eta * dt
+    a, beta, gam = (2 - e * e) / (1 + e), (e - 1) / (1 + e), dt * dt / (1 + e)
+    kap = rho * c * c
+    def phi(cell):
+        ix, iz = cell % nx, cell // nx
+        return (np.sin(np.pi * np.arange(1, nx + 1) * (ix + 1) / (nx + 1))[:, None] *
+                np.sin(np.pi * np.arange(1, nz + 1) * (iz + 1) / (nz + 1))[None, :])
+    norm = (nx + 1) * (nz + 1) / 4.0
+    ps = phi(src) / norm
+    pr = [phi(r) for r in rcv]
+    A0 = np.zeros((nx, nz)); A1 = np.zeros((nx, nz))
+    out = np.zeros((nt, len(rcv)))
+    for n in range(nt):
+        A2 = (a + gam * kap * mu) * A1 + beta * A0 + w[n] * ps
+        out[n] = [np.sum(A2 * p) for p in pr]
+        A0, A1 = A1, A2
+    return out
+
+
+def test_p19_attenuation_modal_closed_form():
+    """Homogeneous medium, uniform attenuation, no absorbing layer: the
+    oracle's traces equal the exact modal solution of the discrete update
+    (≤ 1e-12), and attenuation lowers the late-time amplitude."""
+    nx, nz, nt, h = 22, 18, 300, 1e-3
+    c, rho = 1500.0, 1000.0
+    dt = 0.4 * h / (c * math.sqrt(2))
+    src, rcv = 9 * nx + 7, [9 * nx + 7, 3 * nx + 15, 14 * nx + 2]
+    w = W.ricker(1.0 / (12 * dt), dt, nt)
+    g = W.Geometry(nx=nx, nz=nz, nt=nt, h=h, dt=dt, src=np.array([src], np.int32),
+                   rcv=np.array([rcv], np.int32), npml=0, pml_cref=c)
+    ca, ra = np.full((nz, nx), c), np.full((nz, nx), rho)
+    for eta in (0.0, 3e4):
+        tr = O.run(g, ca, ra, w[None, :], eta=np.full((nz, nx), eta))["traces"][0]
+        ref = _modal_traces(nx, nz, nt, h, dt, c, rho, eta, src, rcv, w)
+        assert rel_l2(tr, ref) <= 1e-12, eta
+    loss = O.run(g, ca, ra, w[None, :], eta=np.full((nz, nx), 3e4))["traces"][0]
+    free = O.run(g, ca, ra, w[None, :])["traces"][0]
+    assert np.linalg.norm(loss[-100:]) < 0.5 * np.linalg.norm(free[-100:])
+
+
+def test_p19_attenuation_brute_force_gradient():
+    m = W.small_random_medium(1, 9, 8, 60, n_tx=2, n_rcv=4, npml=2, dup_receiver=True)
+    g = m.geom
+    rng = np.random.default_rng(5)
+    eta = 2e4 * rng.random(m.c.shape)
+    obs = O.run(g, m.c * (1 + 0.02 * (rng.random(m.c.shape) - 0.5)), m.rho, m.wavelet, eta=1.1 * eta)["traces"]
+    r = O.run(g, m.c, m.rho, m.wavelet, d_obs=obs, eta=eta)
+    J = lambda ee: O.run(g, m.c, m.rho, m.wavelet, d_obs=obs, gradient=False, eta=ee)["misfit"]
+    ge = np.zeros_like(eta)
+    for iz in range(g.nz):
+        for ix in range(g.nx):
+            e = np.zeros_like(eta)
+            e[iz, ix] = eps = 1e-3 * eta[iz, ix] + 1.0
+            ge[iz, ix] = (J(eta + e) - J(eta - e)) / (2 * eps)
+    assert rel_l2(r["grad_eta"], ge) <= 1e-6
+
+
+def test_p19_attenuation_dot_product_and_zero_rate():
+    """<J dm, y> = <dm, J^T y> with dm = (dc, drho, deta) (tangent-linear
+    model against the adjoint's three gradients), and eta = 0 reproduces the
+    loss-free run bitwise."""
+    m = W.small_random_medium(3, 20, 18, 80, n_tx=2, n_rcv=5, npml=3)
+    g = m.geom
+    rng = np.random.default_rng(6)
+    eta = 1e5 * rng.random(m.c.shape)
+    dc, dr = rng.standard_normal(m.c.shape), rng.standard_normal(m.c.shape)
+    de = 1e4 * rng.standard_normal(m.c.shape)
+    y = rng.standard_normal((g.n_tx, g.nt, g.n_rcv))
+    Jdm = O.born(g, m.c, m.rho, m.wavelet, dc, dr, eta=eta, deta=de)
+    r = O.run(g, m.c, m.rho, m.wavelet, d_adj=y, eta=eta)
+    lhs = np.sum(Jdm * y)
+    rhs = np.sum(dc * r["grad_c"]) + np.sum(dr * r["grad_rho"]) + np.sum(de * r["grad_eta"])
+    assert abs(lhs - rhs) <= 1e-10 * abs(lhs)
+    a = O.run(g, m.c, m.rho, m.wavelet, eta=np.zeros_like(m.c))["traces"]
+    assert np.array_equal(a, O.run(g, m.c, m.rho, m.wavelet)["traces"])
