@@ -92,6 +92,9 @@ typedef struct fwi_io {
     void *grad_c;            /* [nz][nx] out dJ/dc, or NULL                                     */
     void *grad_rho;          /* [nz][nx] out dJ/drho, or NULL                                   */
     double *misfit;          /* device double out: J for this medium, or NULL                   */
+    const void *eta;         /* [nz][nx] attenuation rate (1/s, >= 0) of plans created with      */
+                             /*    options.attenuation = 1 (NULL = 0); ignored otherwise         */
+    void *grad_eta;          /* [nz][nx] out dJ/deta (attenuation plans), or NULL               */
 } fwi_io;
 
 typedef struct fwi_options {
@@ -132,6 +135,11 @@ typedef struct fwi_options {
                              /*    as fwi_plan_forward / fwi_plan_adjoint require; 0: with       */
                              /*    ckpt_interval 0 the planner may instead keep every plane and  */
                              /*    run the items in several waves when its cost model prefers it */
+    int32_t attenuation;     /* 1: a per-cell attenuation rate eta (fwi_io.eta) joins the damping */
+                             /*    D of eq. 1-2 (Sec. VII's extension of the forward model) and  */
+                             /*    dJ/deta is returned in grad_eta; one step per launch, order 2, */
+                             /*    not persistent, not hvp                                        */
+    int32_t reserved;
 } fwi_options;
 
 typedef struct fwi_plan fwi_plan;

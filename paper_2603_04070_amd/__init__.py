@@ -96,13 +96,16 @@ class Plan:
     ``launches`` only.  ``single_wave``: keep every item resident at once
     (needed by ``forward`` / ``adjoint``); otherwise an automatic ``ckpt``
     lets the planner trade recompute for waves by its cost model.
+    ``attenuation``: a per-cell attenuation rate (io ``eta``, 1/s) joins the
+    damping term, and ``grad_eta`` returns dJ/deta (one step per launch).
     """
 
     def __init__(self, grids: Sequence[GridSpec], dtype: str = "f32", mode: str = "batched",
                  ckpt: int = 0, group: int = 0, rows: int = 0, use_graph: bool = False,
                  acc_double: bool = False, mem_budget: float = 0.0, steps_per_launch: int = 0,
                  forward_only: bool = False, persistent: bool = False, barrier_spin: int = 0, order: int = 2,
-                 hvp: bool = False, host_only: bool = False, single_wave: bool = False):
+                 hvp: bool = False, host_only: bool = False, single_wave: bool = False,
+                 attenuation: bool = False):
         lib = _lib()
         self.grids = list(grids)
         self.dtype = dtype
@@ -132,6 +135,8 @@ class Plan:
         opt.hvp = int(bool(hvp))
         opt.host_only = int(bool(host_only))
         opt.single_wave = int(bool(single_wave))
+        opt.attenuation = int(bool(attenuation))
+        self.attenuation = bool(attenuation)
         self.order = int(order)
         self.hvp_plan = bool(hvp)
         self._h = C.c_void_p()
@@ -182,7 +187,8 @@ class Plan:
             arr[i] = _abi.FwiIO(_ptr(d["c"]), _ptr(d["rho"]), _ptr(d["wavelet"]),
                                 int(d.get("wavelet_shared", 0)), 0,
                                 _ptr(d.get("d_obs")), _ptr(d.get("d_adj")), _ptr(d["traces"]),
-                                _ptr(d.get("grad_c")), _ptr(d.get("grad_rho")), _ptr(d.get("misfit")))
+                                _ptr(d.get("grad_c")), _ptr(d.get("grad_rho")), _ptr(d.get("misfit")),
+                                _ptr(d.get("eta")), _ptr(d.get("grad_eta")))
         return arr
 
     def _call(self, fn, ios, workspace, stream):
@@ -294,6 +300,9 @@ def gradient(plan: Plan, media: List[dict], workspace=None, stream=None, want_gr
             o["grad_c"] = torch.empty((g.nz, g.nx), dtype=td, device=dev)
             o["grad_rho"] = torch.empty((g.nz, g.nx), dtype=td, device=dev)
             io.update(grad_c=o["grad_c"], grad_rho=o["grad_rho"])
+            if plan.attenuation:
+                o["grad_eta"] = torch.empty((g.nz, g.nx), dtype=td, device=dev)
+                io["grad_eta"] = o["grad_eta"]
         ios.append(io)
         outs.append(o)
     if workspace is None:

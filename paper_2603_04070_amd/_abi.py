@@ -39,6 +39,7 @@ class FwiIO(C.Structure):
         ("wavelet_shared", C.c_int32), ("reserved", C.c_int32),
         ("d_obs", C.c_void_p), ("d_adj", C.c_void_p), ("traces", C.c_void_p),
         ("grad_c", C.c_void_p), ("grad_rho", C.c_void_p), ("misfit", C.c_void_p),
+        ("eta", C.c_void_p), ("grad_eta", C.c_void_p),
     ]
 
 
@@ -52,6 +53,7 @@ class FwiOptions(C.Structure):
         ("tune_cache", C.c_char_p),
         ("order", C.c_int32), ("hvp", C.c_int32),
         ("host_only", C.c_int32), ("single_wave", C.c_int32),
+        ("attenuation", C.c_int32), ("reserved", C.c_int32),
     ]
 
 

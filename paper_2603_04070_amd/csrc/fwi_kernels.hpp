@@ -81,6 +81,7 @@ struct Item {
     const Entry* entries;
     const int32_t* tile_off_x;       // [n_tiles + 1]: receivers inside each tile grown by one cell
     const Entry* entries_x;
+    const T* eatt;                   // [nz*nx] attenuation eta dt added to the damping e, or NULL
 };
 
 template <typename T, int G>
@@ -680,7 +681,9 @@ __device__ void tile_forward(const Item<T, Acc>& it, const Step& st, int tile_x,
             T fw, fe, fn, fs;
             faces<T>(hw, he, iz > 0, hs, bc, bw, be, bn, bs, fw, fe, fn, fs);
             T nb, c2;
-            damp_inc<T>(ex + ldg(it.ez, iz), nb, c2);
+            T e = ex + ldg(it.ez, iz);
+            if (it.eatt) e = e + ldg(it.eatt, x);
+            damp_inc<T>(e, nb, c2);
             const Vec<T, G> vp = vload<T, G>(vin, x);
             Vec<T, G> r, rv;
 #pragma unroll
@@ -715,6 +718,16 @@ __device__ void tile_adjoint(const Item<T, Acc>& it, const Step& st, int tile_x,
     const T* um = it.seg + (int64_t)((t - 2) % it.K) * P;        // u^{t-1}
     Acc* accK = it.acc;
     Acc* accB = it.acc + ncell;
+    // attenuation: the eta term of the imaging also reads u^{t-2} at the cell
+    // (zero before u^1, the segment's checkpoint at its first level)
+    Acc* accE = it.acc + 2 * ncell;
+    const T* um2 = nullptr;
+    if (it.eatt) {
+        const int l2 = t - 2;
+        um2 = l2 <= 0 ? it.zero
+            : (l2 == st.j * it.K && st.j >= 1) ? it.ck + (int64_t)(2 * (st.j - 1) + 1) * P
+            : it.seg + (int64_t)((t - 3) % it.K) * P;
+    }
 
     const int ix = tile_x * kTileX + (int)threadIdx.x;
     const int z0 = tile_z * kWavesZ * rows + (int)threadIdx.y * rows;
@@ -749,10 +762,23 @@ __device__ void tile_adjoint(const Item<T, Acc>& it, const Step& st, int tile_x,
             faces<T>(hw, he, hn, hs, bc, bw, be, bn, bs, fw, fe, fn, fs);
             const T cn = hn ? hf : T(1), cs = hs ? hf : T(1);
             T a, b;
-            damp_coeffs<T>(ex + ldg(it.ez, iz), a, b);
+            T e = ex + ldg(it.ez, iz);
+            if (it.eatt) e = e + ldg(it.eatt, x);
+            damp_coeffs<T>(e, a, b);
             const Vec<T, G> lp = vload<T, G>(p1, x);
             Vec<T, G> r;
-            Acc sk = Acc(0), sb = Acc(0);
+            Acc sk = Acc(0), sb = Acc(0), se = Acc(0);
+            // derivatives of a, beta and gamma/gamma in e for the attenuation term
+            T da = T(0), dbeta = T(0), dgr = T(0), iq = T(0);
+            Vec<T, G> u2 = vzero<T, G>();
+            if (um2) {
+                const T inv = T(1) / (T(1) + e);
+                da = -((e * e + T(2) * e) + T(2)) * (inv * inv);
+                dbeta = T(2) * (inv * inv);
+                dgr = -inv;
+                iq = T(1) / qc;
+                u2 = vload<T, G>(um2, x);
+            }
             // the planes hold w = q lam: the kappa imaging term w0 sum_f b_f du_f
             // is q times the lam one (undone per cell when the gradient is formed)
 #pragma unroll
@@ -763,10 +789,13 @@ __device__ void tile_adjoint(const Item<T, Acc>& it, const Step& st, int tile_x,
                               uC.v[g], uW.v[g], uE.v[g], uN.v[g], uS.v[g], k1, b1);
                 sk += Acc(k1);
                 sb += Acc(b1);
+                // lam (a' u^{t-1} + beta' u^{t-2}) + lam gamma' kappa L u^{t-1}, lam = w / q
+                if (um2) se += Acc((lc.v[g] * iq) * (da * uC.v[g] + dbeta * u2.v[g]) + dgr * k1);
             }
             vstore<T, G>(out, x, r);
             stg(accK, x, ldg(accK, x) + sk);
             stg(accB, x, ldg(accB, x) + sb);
+            if (um2) stg(accE, x, ldg(accE, x) + se);
             ln = lc; lc = ls; uN = uC; uC = uS;
             qc = qs; bn = bc; bc = bs;
         }
@@ -1957,6 +1986,9 @@ struct MediumDev {
     const void* acc0;                 // first accumulator slot of the medium
     int32_t acc_slots;
     int32_t pad3;
+    const T* eta;                     // attenuation rate (1/s), or NULL
+    T* eatt;                          // workspace: eta dt per cell, or NULL
+    T* grad_eta;                      // out dJ/deta, or NULL
 };
 
 __device__ __forceinline__ double dprof(int i, int n, int N, double dmax)
@@ -1986,7 +2018,15 @@ __global__ void prep_kernel(const MediumDev<T>* __restrict__ media, unsigned* st
         const double c = (double)m.c[x], rho = (double)m.rho[x];
         if (!(c > 0.0) || !(rho > 0.0) || !isfinite(c) || !isfinite(rho)) flag |= kFlagMedium;
         if (c > m.c_max) flag |= kFlagCfl;
-        const double e = (dprof(ix, m.nx, m.npml, m.dmax) + dprof(iz, m.nz, m.npml, m.dmax)) * m.dt;
+        double e = (dprof(ix, m.nx, m.npml, m.dmax) + dprof(iz, m.nz, m.npml, m.dmax)) * m.dt;
+        if (m.eatt) {
+            // attenuation joins the damping: gamma below takes it too
+            const double eta = m.eta ? (double)m.eta[x] : 0.0;
+            if (!(eta >= 0.0) || !isfinite(eta)) flag |= kFlagMedium;
+            const T ea = (T)(eta * m.dt);
+            m.eatt[x] = ea;
+            e += (double)ea;
+        }
         const double gam = m.dt * m.dt / (1.0 + e);
         const double q = gam * rho * c * c * ih2 / kRhoRef;
         m.coef[2 * x] = (T)q;
@@ -2070,7 +2110,8 @@ __global__ void finalize_kernel(const MediumDev<T>* __restrict__ media, unsigned
             sb += (double)acc[k * m.acc_stride + n + x];
         }
         const int ix = (int)(x % m.nx), iz = (int)(x / m.nx);
-        const double e = (dprof(ix, m.nx, m.npml, m.dmax) + dprof(iz, m.nz, m.npml, m.dmax)) * m.dt;
+        double e = (dprof(ix, m.nx, m.npml, m.dmax) + dprof(iz, m.nz, m.npml, m.dmax)) * m.dt;
+        if (m.eatt) e += (double)m.eatt[x];
         const double gam = m.dt * m.dt / (1.0 + e);
         // the adjoint kernels carry w = q lam, so the kappa sum is q times
         // the lam one, q the stored coefficient they multiplied by
@@ -2083,6 +2124,14 @@ __global__ void finalize_kernel(const MediumDev<T>* __restrict__ media, unsigned
         if (!isfinite(gc) || !isfinite(gr)) flag |= kFlagNonfinite;
         if (m.grad_c) m.grad_c[x] = (T)gc;
         if (m.grad_rho) m.grad_rho[x] = (T)gr;
+        if (m.eatt) {
+            // dJ/deta = dt dJ/de, the third accumulator of each slot
+            double se = 0.0;
+            for (int k = 0; k < m.acc_slots; ++k) se += (double)acc[k * m.acc_stride + 2 * n + x];
+            const double ge = m.dt * se;
+            if (!isfinite(ge)) flag |= kFlagNonfinite;
+            if (m.grad_eta) m.grad_eta[x] = (T)ge;
+        }
     }
     if (flag) atomicOr(status, flag);
 }

@@ -59,6 +59,7 @@ struct MediumPlan {
     int acc_slots;
     size_t coef_off, acc_off;  // workspace
     size_t wav_off, obs_off, trd_off;   // workspace, hvp plans: dual wavelet, observed and traces
+    size_t eatt_off;           // workspace, attenuation plans: eta dt per cell
     size_t ex_off, ez_off;     // plan tables
 };
 
@@ -71,6 +72,8 @@ struct fwi_plan {
     int Sa = 1;                     // adjoint steps per launch (S: forward-type steps)
     bool acc_double = false;
     bool hvp = false;               // dual-number plan of fwi_plan_hvp
+    bool att = false;               // attenuation rate in the damping (one-step kernels)
+    int nacc = 2;                   // imaging accumulators per cell and slot (S_kappa, S_b[, S_e])
     size_t tsize = 4, asize = 4;
     std::vector<MediumPlan> media;
     std::vector<ItemPlan> items;
@@ -531,6 +534,10 @@ static fwi_status create_impl(fwi_plan* p, fwi_dtype dtype, const fwi_grid* grid
     if (o.hvp != 0 && o.hvp != 1) return fail(p, FWI_ERR_INVALID, "hvp must be 0 or 1");
     if (o.host_only != 0 && o.host_only != 1) return fail(p, FWI_ERR_INVALID, "host_only must be 0 or 1");
     if (o.single_wave != 0 && o.single_wave != 1) return fail(p, FWI_ERR_INVALID, "single_wave must be 0 or 1");
+    if (o.attenuation != 0 && o.attenuation != 1) return fail(p, FWI_ERR_INVALID, "attenuation must be 0 or 1");
+    if (o.attenuation && (o.order == 4 || o.persistent || o.hvp || o.steps_per_launch > 1))
+        return fail(p, FWI_ERR_INVALID, "attenuation runs the second-order operator one step per launch, "
+                                        "not persistent, not hvp");
     if (o.hvp && (o.order == 4 || o.persistent || o.use_graph || o.forward_only || o.steps_per_launch > 1))
         return fail(p, FWI_ERR_INVALID, "hvp plans run the second-order operator one step per launch, "
                                         "not persistent, without graph, not forward-only");
@@ -579,7 +586,7 @@ static fwi_status create_impl(fwi_plan* p, fwi_dtype dtype, const fwi_grid* grid
         p->rows = o.rows ? o.rows : 2;
         if (!two_step_ok(p->rows))
             return fail(p, FWI_ERR_INVALID, "two steps per launch need rows of 1, 2 or 4 whose tile fits the LDS");
-    } else if (o.steps_per_launch == 1 || o.mode == FWI_PLAIN || o.hvp) {
+    } else if (o.steps_per_launch == 1 || o.mode == FWI_PLAIN || o.hvp || o.attenuation) {
         p->S = 1;
         p->rows = o.rows ? o.rows : 4;
     } else {
@@ -590,6 +597,8 @@ static fwi_status create_impl(fwi_plan* p, fwi_dtype dtype, const fwi_grid* grid
     }
     p->acc_double = dtype == FWI_F64 || o.acc_double;
     p->hvp = o.hvp != 0;
+    p->att = o.attenuation != 0;
+    p->nacc = p->att ? 3 : 2;
     // an hvp plan stores (value, derivative) pairs in every field, coefficient and accumulator
     p->tsize = (dtype == FWI_F64 ? 8 : 4) * (p->hvp ? 2 : 1);
     p->asize = (p->acc_double ? 8 : 4) * (p->hvp ? 2 : 1);
@@ -671,8 +680,9 @@ static fwi_status create_impl(fwi_plan* p, fwi_dtype dtype, const fwi_grid* grid
         for (auto& it : p->items) zmax = std::max(zmax, plane_bytes(it));
         fixed += zmax + align_up((size_t)n_media * kMisfitBlocks * sizeof(double));
         for (auto& m : p->media) {
-            fixed += align_up((size_t)m.acc_slots * 2 * m.g.nx * m.g.nz * p->asize) +
+            fixed += align_up((size_t)m.acc_slots * p->nacc * m.g.nx * m.g.nz * p->asize) +
                      align_up((size_t)2 * m.g.nx * m.g.nz * p->tsize);
+            if (p->att) fixed += align_up((size_t)m.g.nx * m.g.nz * p->tsize);
             if (p->hvp)
                 fixed += align_up((size_t)m.g.n_tx * m.g.nt * p->tsize) +
                          2 * align_up((size_t)m.g.n_tx * m.g.nt * m.g.n_rcv * p->tsize);
@@ -841,7 +851,7 @@ static fwi_status create_impl(fwi_plan* p, fwi_dtype dtype, const fwi_grid* grid
     p->acc_region_off = off;
     for (auto& m : p->media) {
         m.acc_off = off;
-        off += align_up((size_t)m.acc_slots * 2 * m.g.nx * m.g.nz * p->asize);
+        off += align_up((size_t)m.acc_slots * p->nacc * m.g.nx * m.g.nz * p->asize);
     }
     p->acc_region_bytes = off - p->acc_region_off;
     p->clear_off = p->zero_off;
@@ -849,6 +859,8 @@ static fwi_status create_impl(fwi_plan* p, fwi_dtype dtype, const fwi_grid* grid
     p->partial_off = off;
     off += align_up((size_t)n_media * kMisfitBlocks * sizeof(double));
     for (auto& m : p->media) { m.coef_off = off; off += align_up((size_t)2 * m.g.nx * m.g.nz * p->tsize); }
+    if (p->att)
+        for (auto& m : p->media) { m.eatt_off = off; off += align_up((size_t)m.g.nx * m.g.nz * p->tsize); }
     if (p->hvp)
         for (auto& m : p->media) {
             const size_t ntr = (size_t)m.g.n_tx * m.g.nt * m.g.n_rcv * p->tsize;
@@ -880,7 +892,8 @@ static fwi_status create_impl(fwi_plan* p, fwi_dtype dtype, const fwi_grid* grid
     p->ws_bytes = off;
     for (auto& it : p->items) {
         const MediumPlan& m = p->media[it.medium];
-        it.acc_off = m.acc_off + (o.mode == FWI_PLAIN ? 0 : (size_t)(&it - &p->items[m.item0]) * 2 * m.g.nx * m.g.nz * p->asize);
+        it.acc_off = m.acc_off + (o.mode == FWI_PLAIN ? 0
+                                  : (size_t)(&it - &p->items[m.item0]) * p->nacc * m.g.nx * m.g.nz * p->asize);
     }
 
     // ---------------- plan tables: profiles, sources, per-tile receiver entries, blocks
@@ -1176,6 +1189,7 @@ void fill_items(fwi_plan* p, const fwi_io* io, unsigned char* ws, bool adj_from_
         d.nlam = p->nlam;
         // the adjoint of the last segment reads levels (J-1)K + 1 .. T of the first pass
         d.keep_from = p->opt.forward_only ? INT_MAX : (ip.J - 1) * ip.K + 1;
+        d.eatt = p->att ? reinterpret_cast<const T*>(ws + m.eatt_off) : nullptr;
         if (p->hvp) {
             // the dual kernels read and write the dual copies in the workspace
             d.wavelet = reinterpret_cast<const T*>(ws + m.wav_off);
@@ -1200,10 +1214,13 @@ void fill_media(fwi_plan* p, const fwi_io* io, unsigned char* ws)
         d.n_tx = m.g.n_tx; d.nt = m.g.nt; d.n_rcv = m.g.n_rcv;
         d.h = m.g.h; d.dt = m.g.dt; d.dmax = m.dmax; d.c_max = m.g.c_max;
         d.npml = m.g.npml;
-        d.acc_stride = 2LL * m.g.nx * m.g.nz;
+        d.acc_stride = (int64_t)p->nacc * m.g.nx * m.g.nz;
         d.c = reinterpret_cast<const T*>(mio.c);
         d.rho = reinterpret_cast<const T*>(mio.rho);
         d.coef = reinterpret_cast<T*>(ws + m.coef_off);
+        d.eta = p->att ? reinterpret_cast<const T*>(mio.eta) : nullptr;
+        d.eatt = p->att ? reinterpret_cast<T*>(ws + m.eatt_off) : nullptr;
+        d.grad_eta = p->att ? reinterpret_cast<T*>(mio.grad_eta) : nullptr;
         d.traces = reinterpret_cast<const T*>(mio.traces);
         d.d_obs = reinterpret_cast<const T*>(mio.d_obs);
         d.grad_c = reinterpret_cast<T*>(mio.grad_c);
@@ -1459,7 +1476,7 @@ fwi_status run_call(fwi_plan* p, const fwi_io* io, void* workspace, size_t bytes
     for (size_t i = 0; i < p->media.size(); ++i) {
         const fwi_io& m = io[i];
         if (!m.c || !m.rho || !m.wavelet || !m.traces) return fail(p, FWI_ERR_INVALID, "c, rho, wavelet and traces are required");
-        const bool g = m.grad_c || m.grad_rho;
+        const bool g = m.grad_c || m.grad_rho || (p->att && m.grad_eta);
         want_grad |= g;
         if (call == kExecute && g && !m.d_obs) return fail(p, FWI_ERR_INVALID, "a gradient needs d_obs");
         if (call == kAdjoint) {

@@ -34,6 +34,13 @@ def oracle_obs(medium_obs, threads=0, ckpt=0):
     return tr.astype(np.float32)
 
 
+def oracle_traces(medium, threads=0, ckpt=0):
+    """The oracle's FP64 traces of ``medium`` (an expected value, not an input)."""
+    import oracle
+    g = medium.geom
+    return oracle.run(g, medium.c, medium.rho, medium.wavelet, ckpt=ckpt, threads=threads)["traces"]
+
+
 def oracle_grad(medium, d_obs, threads=0, ckpt=0):
     import oracle
     g = medium.geom

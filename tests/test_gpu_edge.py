@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 import workloads as W
-from helpers import gpu_run, oracle_grad, oracle_obs, rel_l2, subset
+from helpers import gpu_run, oracle_grad, oracle_obs, oracle_traces, rel_l2, subset
 
 pytestmark = pytest.mark.gpu
 
@@ -52,7 +52,7 @@ def test_zero_residual():
     """Observed data = the oracle's own traces of the same medium: the misfit
     and both gradients vanish to rounding."""
     m = W.small_random_medium(43, 80, 60, 120, n_tx=2, n_rcv=5, npml=3, courant=0.5)
-    obs = oracle_obs(m)
+    obs = oracle_traces(m)                     # FP64: exactly F(m) for both sides
     res, _ = gpu_run([m], [obs], dtype="f64", ckpt=7)
     scale = float(np.sum(obs ** 2))
     assert float(res[0]["misfit"][0]) <= 1e-20 * scale

@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 import workloads as W
-from helpers import oracle_obs, rel_l2, subset
+from helpers import oracle_obs, oracle_traces, rel_l2, subset
 
 pytestmark = pytest.mark.gpu
 
@@ -75,7 +75,7 @@ def test_hvp_fp64_zero_residual_gauss_newton():
     adjoint of twice its tangent-linear traces: agreement at 1e-10."""
     import oracle
     m, _, dc, drho = _case(12, 90, 64, 140, 2)
-    obs0 = oracle_obs(m)
+    obs0 = oracle_traces(m)                    # FP64: exactly F(m), a zero residual
     print("[hvp] f64 zero residual 90x64 nt 140", flush=True)
     res, _ = _gpu([m], [obs0], [(dc, drho)], "f64", ckpt=9)
     dd = oracle.born(m.geom, m.c, m.rho, m.wavelet, dc, drho)

@@ -4,7 +4,7 @@ import numpy as np
 import pytest
 
 import workloads as W
-from helpers import gpu_run, oracle_grad, oracle_obs, rel_l2, subset
+from helpers import gpu_run, oracle_grad, oracle_obs, oracle_traces, rel_l2, subset
 
 pytestmark = pytest.mark.gpu
 
@@ -60,7 +60,7 @@ def test_fourth_order_differs_from_second():
     """The plan's order reaches the kernels: order-2 GPU traces differ from
     the order-4 oracle by far more than rounding."""
     m = _medium(8, 96, 70, 150, n_tx=2, n_rcv=5, npml=3, courant=0.45)
-    ref = oracle_obs(m)
+    ref = oracle_traces(m)
     r4, _ = gpu_run([m], None, dtype="f64", order=4)
     r2, _ = gpu_run([m], None, dtype="f64", order=2)
     assert rel_l2(r4[0]["traces"], ref) <= 1e-10
