@@ -346,7 +346,7 @@ def main():
         "hbm_roofline_pct": round(100.0 * value * 1e9 * BYTES_PER_UPDATE / (HBM_PEAK_GBS * 1e9), 2),
         "roofline": {
             "bound": "hbm",
-            "kernel": ("step kernels (fwd4_kernel, adj4_kernel): 24 B per update each" if args.order == 4 else
+            "kernel": ("step kernels (fwd4x2_kernel, fwd4_kernel, adj4_kernel): 24 B per update each" if args.order == 4 else
                        "step kernels (fwd3_kernel, fwd2_kernel, adj2_kernel, fwd1_kernel, adj1_kernel): "
                        "24 B per update each"),
             "achieved": round(achieved, 1),

@@ -108,8 +108,9 @@ typedef struct fwi_options {
                              /*    replay it (FWI_BATCHED only)                                  */
     int32_t acc_double;      /* 1: imaging accumulators in double for FWI_F32 (default 0)       */
     int32_t steps_per_launch;/* forward-type time steps fused per launch: 0 = default (3 batched, */
-                             /*    2 persistent, 1 plain), 1, 2 or 3.  Adjoint launches fuse     */
-                             /*    min(this, 2) steps.  2 or 3 fall back to 1 when a wrapping    */
+                             /*    2 persistent, 1 plain; order 4: 1), 1, 2 or 3 (order 4: 1 or  */
+                             /*    2).  Adjoint launches fuse min(this, 2) steps (order 4: one). */
+                             /*    2 or 3 fall back to 1 when a wrapping                         */
                              /*    segment buffer has K < 4; with 2 or 3, rows must be 1, 2 or 4; */
                              /*    3 is not persistent                                           */
     int32_t forward_only;    /* 1: traces and misfit only; no replay state is kept and           */
@@ -122,9 +123,8 @@ typedef struct fwi_options {
     double mem_budget;       /* bytes the workspace may use; 0 = 60% of free device memory      */
     const char *tune_cache;  /* JSON cache path of the tile autotuner, or NULL                   */
     int32_t order;           /* spatial order of the operator: 0 or 2 = the 5-point flux form of */
-                             /*    eq. 1-2; 4 = staggered fourth-order differences (one step per */
-                             /*    launch, rows 1, 2 or 4, not persistent; stability bound with  */
-                             /*    98/9 in place of 8)                                           */
+                             /*    eq. 1-2; 4 = staggered fourth-order differences (rows 1, 2 or */
+                             /*    4, not persistent; stability bound with 98/9 in place of 8)   */
     int32_t hvp;             /* 1: the plan serves fwi_plan_hvp only (one step per launch, order */
                              /*    2, not persistent, no graph, not forward_only; its workspace  */
                              /*    holds value and derivative of every field)                    */
@@ -256,7 +256,8 @@ typedef enum fwi_kernel {
     FWI_K_FWD4 = 5, FWI_K_ADJ4 = 6,          /* fourth-order operator, one step */
     FWI_K_PERSISTENT = 7, FWI_K_FILL = 8, FWI_K_PREP = 9, FWI_K_MISFIT_PARTIAL = 10,
     FWI_K_MISFIT_FINAL = 11, FWI_K_FINALIZE = 12,
-    FWI_K_PREP_HVP = 13, FWI_K_PACK_HVP = 14, FWI_K_UNPACK_HVP = 15, FWI_K_FINALIZE_HVP = 16
+    FWI_K_PREP_HVP = 13, FWI_K_PACK_HVP = 14, FWI_K_UNPACK_HVP = 15, FWI_K_FINALIZE_HVP = 16,
+    FWI_K_FWD4X2 = 17                         /* fourth-order operator, two forward steps */
 } fwi_kernel;
 
 typedef struct fwi_launch {

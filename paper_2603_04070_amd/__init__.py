@@ -90,7 +90,8 @@ class Plan:
     ``steps_per_launch``: forward-type steps fused per launch (0 =
     automatic: 3 batched, 1 plain; adjoint launches fuse at most 2).
     ``order``: 2 (the 5-point flux form) or 4 (staggered fourth-order
-    differences, one step per launch).  ``hvp``: the plan serves
+    differences: one forward-type step per launch, or two with
+    ``steps_per_launch=2``; one adjoint step).  ``hvp``: the plan serves
     ``hessian_vector`` (fwi_plan_hvp) only.  ``host_only``: plan on the host
     without any HIP call (needs ``mem_budget``): sizes, ``info`` and
     ``launches`` only.  ``single_wave``: keep every item resident at once

@@ -67,7 +67,7 @@ class FwiLaunch(C.Structure):
 
 KERNEL_NAMES = ("fwd1", "fwd2", "adj1", "adj2", "fwd3", "fwd4", "adj4", "persistent", "fill", "prep",
                 "misfit_partial", "misfit_final", "finalize", "prep_hvp", "pack_hvp", "unpack_hvp",
-                "finalize_hvp")
+                "finalize_hvp", "fwd4x2")
 
 
 class FwiHvpIO(C.Structure):

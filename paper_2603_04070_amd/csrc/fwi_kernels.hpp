@@ -54,6 +54,40 @@ struct Entry {
     int32_t pad;
 };
 
+// Quotient of a non-negative 31-bit value by a divisor d >= 1 fixed at plan
+// creation, as a multiply-high and a shift (Granlund and Montgomery,
+// "Division by invariant integers using multiplication", 1994, Thm. 4.2 with
+// N = 32): with l = ceil(log2 d) and m = floor(2^32 (2^l - d) / d) + 1 (below
+// 2^32), floor(n / d) = (mulhi(m, n) + n) >> l for 0 <= n < 2^31, where the
+// sum stays below 2^32.  Wave-uniform operands keep it on the scalar unit;
+// the hardware has no integer divide, so n / d with d known only at run time
+// costs a dozen vector instructions and a long dependent chain.
+struct Div {
+    uint32_t m, l;
+};
+
+inline Div make_div(uint32_t d)
+{
+    uint32_t l = 0;
+    while ((1ull << l) < d) ++l;
+    return Div{(uint32_t)((((1ull << 32) * ((1ull << l) - d)) / d) + 1), l};
+}
+
+__host__ __device__ __forceinline__ int quo(int n, Div v)
+{
+    const uint32_t t = (uint32_t)(((uint64_t)(uint32_t)n * v.m) >> 32);
+    return (int)((t + (uint32_t)n) >> v.l);
+}
+
+// Schedule constants of an item (T steps, interval K, J segments, S
+// forward-type and Sa adjoint steps per launch): the launch counts of its
+// runs and the dividers that decoding a launch index needs.
+struct Sched {
+    int32_t T, K, J, S, Sa;
+    int32_t nf, last, nl, nkf, nb;   // forward launches, last segment's levels and adjoint launches, per-segment counts
+    Div dK, dnb;
+};
+
 template <typename T, typename Acc>
 struct Item {
     int32_t nx, nz, nt, g_used;      // g_used <= G real transmits
@@ -82,6 +116,8 @@ struct Item {
     const int32_t* tile_off_x;       // [n_tiles + 1]: receivers inside each tile grown by one cell
     const Entry* entries_x;
     const T* eatt;                   // [nz*nx] attenuation eta dt added to the damping e, or NULL
+    Sched sc;                        // schedule constants (nt, K, J, S, Sa)
+    Div dtx, dnx;                    // dividers by tiles_x and nx
 };
 
 template <typename T, int G>
@@ -369,6 +405,56 @@ __host__ __device__ inline Step decode(int T, int K, int J, int s, int S, int Sa
     return r;
 }
 
+inline Sched make_sched(int T, int K, int J, int S, int Sa)
+{
+    Sched c{};
+    c.T = T; c.K = K; c.J = J; c.S = S; c.Sa = Sa;
+    c.nf = (T + S - 1) / S;
+    c.last = T - (J - 1) * K;
+    c.nl = (c.last + Sa - 1) / Sa;
+    c.nkf = (K + S - 1) / S;
+    c.nb = c.nkf + (K + Sa - 1) / Sa;
+    c.dK = make_div((uint32_t)K);
+    c.dnb = make_div((uint32_t)c.nb);
+    return c;
+}
+
+// decode() from the precomputed constants: the same step for every s, with
+// no division left to the lanes.
+__host__ __device__ inline Step decode_s(const Sched& c, int s)
+{
+    Step r{kIdle, 0, 0, 0};
+    if (s < 0) return r;
+    if (s < c.nf) {
+        r.phase = kFwd; r.n = s * c.S; r.j = quo(r.n, c.dK); r.count = imin(c.S, c.T - r.n);
+        return r;
+    }
+    s -= c.nf;
+    if (s < c.nl) {
+        r.phase = kAdj; r.n = c.T + 1 - s * c.Sa; r.j = c.J - 1; r.count = imin(c.Sa, c.last - s * c.Sa);
+        return r;
+    }
+    s -= c.nl;
+    if (s < c.nb * (c.J - 1)) {
+        const int blk = quo(s, c.dnb), rem = s - blk * c.nb;
+        r.j = c.J - 2 - blk;
+        if (rem < c.nkf) {
+            r.phase = kRecomp; r.n = r.j * c.K + rem * c.S; r.count = imin(c.S, c.K - rem * c.S);
+        } else {
+            const int m = rem - c.nkf;
+            r.phase = kAdj; r.n = r.j * c.K + c.K + 1 - m * c.Sa; r.count = imin(c.Sa, c.K - m * c.Sa);
+        }
+    }
+    return r;
+}
+
+// x mod K of an item for x >= 0.
+template <typename I>
+__device__ __forceinline__ int kmod(const I& it, int x)
+{
+    return x - quo(x, it.sc.dK) * it.K;
+}
+
 // The per-cell arithmetic below spells out every fused multiply-add and
 // disables contraction, so that every kernel (one step per launch, either
 // half of a two-step launch, first pass or recompute) rounds a cell exactly
@@ -488,7 +574,7 @@ __device__ __forceinline__ const T* fwd_plane(const Item<T, Acc>& it, const Step
 {
     if (tau <= 0) return it.zero;
     if (st.phase == kRecomp && tau == st.j * it.K) return it.ck + (int64_t)(2 * (st.j - 1) + 1) * it.plane;
-    return it.seg + (int64_t)((tau - 1) % it.K) * it.plane;
+    return it.seg + (int64_t)kmod(it, tau - 1) * it.plane;
 }
 
 // v slot of level tau in a run of forward-type launches.  A launch of two or
@@ -530,8 +616,9 @@ __device__ __forceinline__ T* vel_out(const Item<T, Acc>& it, const Step& st, in
 template <typename T, typename Acc>
 __device__ __forceinline__ T* ckpt_pair(const Item<T, Acc>& it, const Step& st, int t1)
 {
-    if (st.phase != kFwd || t1 % it.K != 0) return nullptr;
-    const int j = t1 / it.K;
+    if (st.phase != kFwd) return nullptr;
+    const int j = quo(t1, it.sc.dK);
+    if (t1 != j * it.K) return nullptr;
     if (j < 1 || j > it.J - 1) return nullptr;
     return it.ck + (int64_t)(2 * (j - 1)) * it.plane;
 }
@@ -552,6 +639,34 @@ __device__ __forceinline__ Src<T, G> sources(const Item<T, Acc>& it, int n)
         s.w[g] = s.cell[g] >= 0 ? ldg(it.wavelet, (int64_t)(it.tx0 + g) * it.wavelet_stride + n) : T(0);
     }
     return s;
+}
+
+// Whether a source cell of s lies in the tile-relative columns [xa, xb) and
+// rows [za, zb) of the tile at (x0, z0): where none does, the launch skips the
+// per-cell source test (a wave-uniform branch).
+template <typename T, int G, typename Acc>
+__device__ __forceinline__ bool src_near(const Src<T, G>& s, const Item<T, Acc>& it, int x0, int z0, int xa, int xb,
+                                         int za, int zb)
+{
+    bool any = false;
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        const int c = s.cell[g];
+        if (c >= 0) {
+            const int cz = quo(c, it.dnx), cx = c - cz * it.nx;
+            any = any || (cx >= x0 + xa && cx < x0 + xb && cz >= z0 + za && cz < z0 + zb);
+        }
+    }
+    return any;
+}
+
+// v += w at this cell for the transmits whose source it is.
+template <typename T, int G>
+__device__ __forceinline__ void add_src(Vec<T, G>& v, int cell, const Src<T, G>& s)
+{
+#pragma unroll
+    for (int g = 0; g < G; ++g)
+        if (cell == s.cell[g]) v.v[g] += s.w[g];
 }
 
 __device__ __forceinline__ Entry ld_entry(const Entry* p, int i)
@@ -598,7 +713,7 @@ __device__ __forceinline__ void sample_tile2(const Item<T, Acc>& it, Span sp, in
     for (int e = sp.e0 + tid; e < sp.e1; e += kBlock) {
         const Entry en = ld_entry(it.entries, e);
         const int cell = en.slot / G, g = en.slot - cell * G;
-        const int k = (cell / it.nx - z0 + 1) * W1 + (cell % it.nx - x0 + 1);
+        const int k = (quo(cell, it.dnx) - z0 + 1) * W1 + (cell - quo(cell, it.dnx) * it.nx - x0 + 1);
         stg(it.traces, en.trace_off + (int64_t)n * it.n_rcv, U1[k].v[g]);
         stg(it.traces, en.trace_off + (int64_t)(n + 1) * it.n_rcv, ldg(out2, en.slot));
     }
@@ -651,11 +766,13 @@ __device__ void tile_forward(const Item<T, Acc>& it, const Step& st, int tile_x,
     const int nx = it.nx, nz = it.nz, n = st.n;
     const T* cur = fwd_plane(it, st, n);
     const T* vin = vel_in(it, st, n);
-    T* out = it.seg + (int64_t)(n % it.K) * it.plane;
+    T* out = it.seg + (int64_t)kmod(it, n) * it.plane;
     T* vout = vel_out(it, st, n + 1);
     T* ckv = ckpt_pair(it, st, n + 1);
     T* cku = ckv ? ckv + it.plane : nullptr;
     const Src<T, G> src = sources<T, G>(it, n);
+    const bool near = src_near<T, G, Acc>(src, it, tile_x * kTileX, tile_z * kWavesZ * rows, 0, kTileX, 0,
+                                          kWavesZ * rows);
 
     const int ix = tile_x * kTileX + (int)threadIdx.x;
     const int z0 = tile_z * kWavesZ * rows + (int)threadIdx.y * rows;
@@ -687,12 +804,11 @@ __device__ void tile_forward(const Item<T, Acc>& it, const Step& st, int tile_x,
             const Vec<T, G> vp = vload<T, G>(vin, x);
             Vec<T, G> r, rv;
 #pragma unroll
-            for (int g = 0; g < G; ++g) {
-                T v = fwd_cell<T>(nb, c2, q, fw, fe, fn, fs, uc.v[g], uw.v[g], ue.v[g], un.v[g], us.v[g], vp.v[g]);
-                if ((int)x == src.cell[g]) v += src.w[g];
-                rv.v[g] = v;
-                r.v[g] = uc.v[g] + v;
-            }
+            for (int g = 0; g < G; ++g)
+                rv.v[g] = fwd_cell<T>(nb, c2, q, fw, fe, fn, fs, uc.v[g], uw.v[g], ue.v[g], un.v[g], us.v[g], vp.v[g]);
+            if (near) add_src<T, G>(rv, (int)x, src);
+#pragma unroll
+            for (int g = 0; g < G; ++g) r.v[g] = uc.v[g] + rv.v[g];
             vstore<T, G>(out, x, r);
             vstore<T, G>(vout, x, rv);
             if (ckv) {
@@ -712,10 +828,10 @@ __device__ void tile_adjoint(const Item<T, Acc>& it, const Step& st, int tile_x,
 {
     const int nx = it.nx, nz = it.nz, t = st.n;
     const int64_t P = it.plane, ncell = (int64_t)nx * nz;
-    const T* cur = it.lam + (int64_t)(t % it.nlam) * P;          // w^t = q lam^t
-    const T* p1 = it.lam + (int64_t)((t + 1) % it.nlam) * P;     // w^{t+1}
-    T* out = it.lam + (int64_t)((t - 1) % it.nlam) * P;          // w^{t-1} (in place when nlam = 2)
-    const T* um = it.seg + (int64_t)((t - 2) % it.K) * P;        // u^{t-1}
+    const T* cur = it.lam + (int64_t)(t & (it.nlam - 1)) * P;          // w^t = q lam^t
+    const T* p1 = it.lam + (int64_t)((t + 1) & (it.nlam - 1)) * P;     // w^{t+1}
+    T* out = it.lam + (int64_t)((t - 1) & (it.nlam - 1)) * P;          // w^{t-1} (in place when nlam = 2)
+    const T* um = it.seg + (int64_t)kmod(it, t - 2) * P;        // u^{t-1}
     Acc* accK = it.acc;
     Acc* accB = it.acc + ncell;
     // attenuation: the eta term of the imaging also reads u^{t-2} at the cell
@@ -726,7 +842,7 @@ __device__ void tile_adjoint(const Item<T, Acc>& it, const Step& st, int tile_x,
         const int l2 = t - 2;
         um2 = l2 <= 0 ? it.zero
             : (l2 == st.j * it.K && st.j >= 1) ? it.ck + (int64_t)(2 * (st.j - 1) + 1) * P
-            : it.seg + (int64_t)((t - 3) % it.K) * P;
+            : it.seg + (int64_t)kmod(it, t - 3) * P;
     }
 
     const int ix = tile_x * kTileX + (int)threadIdx.x;
@@ -884,8 +1000,8 @@ __device__ void tile_forward2(const Item<T, Acc>& it, const Step& st, int tile_x
     T* D = B0 + L::N0;                                                   // damping
     const T* cur = fwd_plane(it, st, n);
     const T* vin = vel_in(it, st, n);
-    T* out1 = it.seg + (int64_t)(n % it.K) * it.plane;
-    T* out2 = it.seg + (int64_t)((n + 1) % it.K) * it.plane;
+    T* out1 = it.seg + (int64_t)kmod(it, n) * it.plane;
+    T* out2 = it.seg + (int64_t)kmod(it, n + 1) * it.plane;
     T* vout = vel_out(it, st, n + 2);
     T* ck1 = ckpt_pair(it, st, n + 1);
     T* ck2 = ckpt_pair(it, st, n + 2);
@@ -898,6 +1014,8 @@ __device__ void tile_forward2(const Item<T, Acc>& it, const Step& st, int tile_x
     const Src<T, G> s2 = sources<T, G>(it, n + 1);
     const Span rcv = sample ? span_of(it.tile_off, tile_z * it.tiles_x + tile_x) : Span{0, 0};
     const int x0 = tile_x * kTileX, z0 = tile_z * L::TZ;
+    // a source within the cells this launch updates (step n on the tile grown by one)
+    const bool near = src_near<T, G, Acc>(s1, it, x0, z0, -1, kTileX + 1, -1, L::TZ + 1);
     const int tid = threadIdx.y * kTileX + threadIdx.x;
     const int ix = x0 + (int)threadIdx.x;
     const T* cf = it.coef;
@@ -958,12 +1076,11 @@ __device__ void tile_forward2(const Item<T, Acc>& it, const Step& st, int tile_x
         const Vec<T, G> u0 = U0[k], uw = U0[k - 1], ue = U0[k + 1], un = U0[k - L::W0], us = U0[k + L::W0];
         Vec<T, G> r;
 #pragma unroll
-        for (int g = 0; g < G; ++g) {
-            T v = fwd_cell<T>(nb, c2, q, fw, fe, fn, fs, u0.v[g], uw.v[g], ue.v[g], un.v[g], us.v[g], vv.v[g]);
-            if ((int)x == s1.cell[g]) v += s1.w[g];
-            vv.v[g] = v;
-            r.v[g] = u0.v[g] + v;
-        }
+        for (int g = 0; g < G; ++g)
+            vv.v[g] = fwd_cell<T>(nb, c2, q, fw, fe, fn, fs, u0.v[g], uw.v[g], ue.v[g], un.v[g], us.v[g], vv.v[g]);
+        if (near) add_src<T, G>(vv, (int)x, s1);
+#pragma unroll
+        for (int g = 0; g < G; ++g) r.v[g] = u0.v[g] + vv.v[g];
         return r;
     };
     // step n: the ring (u^{n+1} for LDS only), then the tile cells of this
@@ -1010,12 +1127,12 @@ __device__ void tile_forward2(const Item<T, Acc>& it, const Step& st, int tile_x
                                 us = U1[k1 + L::W1];
                 Vec<T, G> r, rv;
 #pragma unroll
-                for (int g = 0; g < G; ++g) {
-                    T v = fwd_cell<T>(nb, c2, q, fw, fe, fn, fs, u0.v[g], uw.v[g], ue.v[g], un.v[g], us.v[g], vt[k].v[g]);
-                    if ((int)x == s2.cell[g]) v += s2.w[g];
-                    rv.v[g] = v;
-                    r.v[g] = u0.v[g] + v;
-                }
+                for (int g = 0; g < G; ++g)
+                    rv.v[g] = fwd_cell<T>(nb, c2, q, fw, fe, fn, fs, u0.v[g], uw.v[g], ue.v[g], un.v[g], us.v[g],
+                                          vt[k].v[g]);
+                if (near) add_src<T, G>(rv, (int)x, s2);
+#pragma unroll
+                for (int g = 0; g < G; ++g) r.v[g] = u0.v[g] + rv.v[g];
                 vstore32<T, G>(out2, x, r);
                 vstore32<T, G>(vout, x, rv);
                 if (ck2) {
@@ -1069,7 +1186,7 @@ __device__ __forceinline__ void sample_lds(const Item<T, Acc>& it, Span sp, int 
     for (int e = sp.e0 + tid; e < sp.e1; e += kBlock) {
         const Entry en = ld_entry(it.entries, e);
         const int cell = en.slot / G, g = en.slot - cell * G;
-        const int k = (cell / it.nx - z0 + GROW) * W + (cell % it.nx - x0 + GROW);
+        const int k = (quo(cell, it.dnx) - z0 + GROW) * W + (cell - quo(cell, it.dnx) * it.nx - x0 + GROW);
         stg(it.traces, en.trace_off + (int64_t)m * it.n_rcv, U[k].v[g]);
     }
 }
@@ -1087,9 +1204,9 @@ __device__ void tile_forward3(const Item<T, Acc>& it, const Step& st, int tile_x
     T* D = B + L::N3;                                                    // damping
     const T* cur = fwd_plane(it, st, n);
     const T* vin = vel_in(it, st, n);
-    T* out1 = it.seg + (int64_t)(n % it.K) * it.plane;
-    T* out2 = it.seg + (int64_t)((n + 1) % it.K) * it.plane;
-    T* out3 = it.seg + (int64_t)((n + 2) % it.K) * it.plane;
+    T* out1 = it.seg + (int64_t)kmod(it, n) * it.plane;
+    T* out2 = it.seg + (int64_t)kmod(it, n + 1) * it.plane;
+    T* out3 = it.seg + (int64_t)kmod(it, n + 2) * it.plane;
     T* vout = vel_out(it, st, n + 3);
     T* ck1 = ckpt_pair(it, st, n + 1);
     T* ck2 = ckpt_pair(it, st, n + 2);
@@ -1102,6 +1219,8 @@ __device__ void tile_forward3(const Item<T, Acc>& it, const Step& st, int tile_x
     const Src<T, G> s3 = sources<T, G>(it, n + 2);
     const Span rcv = sample ? span_of(it.tile_off, tile_z * it.tiles_x + tile_x) : Span{0, 0};
     const int x0 = tile_x * kTileX, z0 = tile_z * L::TZ;
+    // a source within the cells this launch updates (step n on the tile grown by two)
+    const bool near = src_near<T, G, Acc>(s1, it, x0, z0, -2, kTileX + 2, -2, L::TZ + 2);
     const int tid = threadIdx.y * kTileX + threadIdx.x;
     const int tx = (int)threadIdx.x, ix = x0 + tx;
     const T* cf = it.coef;
@@ -1166,12 +1285,11 @@ __device__ void tile_forward3(const Item<T, Acc>& it, const Step& st, int tile_x
         const Vec<T, G> u0 = U[k], uw = U[k - 1], ue = U[k + 1], un = U[k - W], us = U[k + W];
         Vec<T, G> r;
 #pragma unroll
-        for (int g = 0; g < G; ++g) {
-            T v = fwd_cell<T>(nb, c2, qc, fw, fe, fn, fs, u0.v[g], uw.v[g], ue.v[g], un.v[g], us.v[g], vv.v[g]);
-            if (cell == sc.cell[g]) v += sc.w[g];
-            vv.v[g] = v;
-            r.v[g] = u0.v[g] + v;
-        }
+        for (int g = 0; g < G; ++g)
+            vv.v[g] = fwd_cell<T>(nb, c2, qc, fw, fe, fn, fs, u0.v[g], uw.v[g], ue.v[g], un.v[g], us.v[g], vv.v[g]);
+        if (near) add_src<T, G>(vv, cell, sc);
+#pragma unroll
+        for (int g = 0; g < G; ++g) r.v[g] = u0.v[g] + vv.v[g];
         return r;
     };
     auto lds_at = [&](int x, int z) { return (z + 3) * W + x + 3; };
@@ -1265,12 +1383,12 @@ __device__ void tile_adjoint2(const Item<T, Acc>& it, const Step& st, int tile_x
     Vec<T, G>* X = reinterpret_cast<Vec<T, G>*>(B0 + L::N0) - 1;
     Vec<T, G>* Y = X + (L::N1 - 2);
     T* D = reinterpret_cast<T*>(Y + (L::N1 - 1));                        // damping
-    const T* cur = it.lam + (int64_t)(t % nl) * P;
-    const T* p1 = it.lam + (int64_t)((t + 1) % nl) * P;
-    T* out1 = it.lam + (int64_t)((t - 1) % nl) * P;
-    T* out2 = it.lam + (int64_t)((t - 2) % nl) * P;
-    const T* um1 = it.seg + (int64_t)((t - 2) % it.K) * P;
-    const T* um2 = it.seg + (int64_t)((t - 3) % it.K) * P;
+    const T* cur = it.lam + (int64_t)(t & (nl - 1)) * P;
+    const T* p1 = it.lam + (int64_t)((t + 1) & (nl - 1)) * P;
+    T* out1 = it.lam + (int64_t)((t - 1) & (nl - 1)) * P;
+    T* out2 = it.lam + (int64_t)((t - 2) & (nl - 1)) * P;
+    const T* um1 = it.seg + (int64_t)kmod(it, t - 2) * P;
+    const T* um2 = it.seg + (int64_t)kmod(it, t - 3) * P;
     const int x0 = tile_x * kTileX, z0 = tile_z * L::TZ;
     const int tid = threadIdx.y * kTileX + threadIdx.x;
     const int tile = tile_z * it.tiles_x + tile_x;
@@ -1409,7 +1527,7 @@ __device__ void tile_adjoint2(const Item<T, Acc>& it, const Step& st, int tile_x
             T sum = T(0);
             for (int k = 0; k < en.run; ++k) sum += adj_source(it, ld_entry(it.entries_x, e + k), t - 2);
             const int cell = en.slot / G, g = en.slot - cell * G;
-            const int ex = cell % nx - (x0 - 1), ez = cell / nx - (z0 - 1);
+            const int cz = quo(cell, it.dnx), ex = cell - cz * nx - (x0 - 1), ez = cz - (z0 - 1);
             const int c = ez * L::W1 + ex;
             if (c > 0 && c < L::N1 - 1) X[c].v[g] += Q0[(ez + 1) * L::W0 + ex + 1] * sum;
         }
@@ -1471,9 +1589,7 @@ __device__ void tile_adjoint2(const Item<T, Acc>& it, const Step& st, int tile_x
 template <typename T, typename Acc>
 __device__ __forceinline__ Step item_step(const Item<T, Acc>& it, int s, int mode)
 {
-    int sl = s;
-    if (mode == kRunAdjOnly) sl = s + (it.nt + it.S - 1) / it.S;
-    Step st = decode(it.nt, it.K, it.J, sl, it.S, it.Sa);
+    Step st = decode_s(it.sc, mode == kRunAdjOnly ? s + it.sc.nf : s);
     if (mode == kRunFwdOnly && st.phase != kFwd) st.phase = kIdle;
     return st;
 }
@@ -1488,7 +1604,7 @@ __global__ __launch_bounds__(kBlock) void fwd1_kernel(const Item<T, Acc>* __rest
     const Item<T, Acc>& it = items[bt.x];
     const Step st = item_step(it, s, mode);
     if ((st.phase != kFwd && st.phase != kRecomp) || st.count != 1) return;
-    tile_forward<T, G, Acc>(it, st, bt.y % it.tiles_x, bt.y / it.tiles_x, rows, st.phase == kFwd && it.sample);
+    tile_forward<T, G, Acc>(it, st, bt.y - quo(bt.y, it.dtx) * it.tiles_x, quo(bt.y, it.dtx), rows, st.phase == kFwd && it.sample);
 }
 
 // Forward-type launches of two steps, tiles of 64 x 4R cells.
@@ -1502,7 +1618,7 @@ __global__ __launch_bounds__(kBlock) void fwd2_kernel(const Item<T, Acc>* __rest
     const Item<T, Acc>& it = items[bt.x];
     const Step st = item_step(it, s, mode);
     if ((st.phase != kFwd && st.phase != kRecomp) || st.count != 2) return;
-    tile_forward2<T, G, Acc, R>(it, st, bt.y % it.tiles_x, bt.y / it.tiles_x, st.phase == kFwd && it.sample, smem);
+    tile_forward2<T, G, Acc, R>(it, st, bt.y - quo(bt.y, it.dtx) * it.tiles_x, quo(bt.y, it.dtx), st.phase == kFwd && it.sample, smem);
 }
 
 // Forward-type launches of three steps, tiles of 64 x 4R cells.
@@ -1516,7 +1632,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(Lds3<T, 
     const Item<T, Acc>& it = items[bt.x];
     const Step st = item_step(it, s, mode);
     if ((st.phase != kFwd && st.phase != kRecomp) || st.count != 3) return;
-    tile_forward3<T, G, Acc, R>(it, st, bt.y % it.tiles_x, bt.y / it.tiles_x, st.phase == kFwd && it.sample, smem);
+    tile_forward3<T, G, Acc, R>(it, st, bt.y - quo(bt.y, it.dtx) * it.tiles_x, quo(bt.y, it.dtx), st.phase == kFwd && it.sample, smem);
 }
 
 // Adjoint + imaging launches of one step.
@@ -1529,7 +1645,7 @@ __global__ __launch_bounds__(kBlock) void adj1_kernel(const Item<T, Acc>* __rest
     const Item<T, Acc>& it = items[bt.x];
     const Step st = item_step(it, s, mode);
     if (st.phase != kAdj || st.count != 1) return;
-    tile_adjoint<T, G, Acc>(it, st, bt.y % it.tiles_x, bt.y / it.tiles_x, rows);
+    tile_adjoint<T, G, Acc>(it, st, bt.y - quo(bt.y, it.dtx) * it.tiles_x, quo(bt.y, it.dtx), rows);
 }
 
 // Adjoint + imaging launches of two steps, tiles of 64 x 4R cells.
@@ -1543,7 +1659,7 @@ __global__ __launch_bounds__(kBlock) void adj2_kernel(const Item<T, Acc>* __rest
     const Item<T, Acc>& it = items[bt.x];
     const Step st = item_step(it, s, mode);
     if (st.phase != kAdj || st.count != 2) return;
-    tile_adjoint2<T, G, Acc, R>(it, st, bt.y % it.tiles_x, bt.y / it.tiles_x, smem);
+    tile_adjoint2<T, G, Acc, R>(it, st, bt.y - quo(bt.y, it.dtx) * it.tiles_x, quo(bt.y, it.dtx), smem);
 }
 
 // ============================================================== fourth-order variant
@@ -1552,19 +1668,33 @@ __global__ __launch_bounds__(kBlock) void adj2_kernel(const Item<T, Acc>* __rest
 // cells j and j+1 of a row or column is bt_f (9/8 (u_{j+1} - u_j) - 1/24
 // (u_{j+2} - u_{j-1})) with bt_f the mean of the two cells' bt, and the
 // operator is 9/8 (F_{+1/2} - F_{-1/2}) - 1/24 (F_{+3/2} - F_{-3/2}) summed
-// over both axes, so it reaches three cells out.  One step per launch: the
-// tile (64 x 4R cells) is staged in LDS grown by three cells.  Outside the
-// grid the fields are zero and bt repeats the nearest in-grid cell of the
-// row or column (the staged value at the clamped position), the border rule
-// of the second-order operator carried to the wider stencil.
+// over both axes, so it reaches three cells out.  Outside the grid the
+// fields are zero and bt repeats the nearest in-grid cell of the row or
+// column (the staged value at the clamped position), the border rule of the
+// second-order operator carried to the wider stencil.
+//
+// A face's flux enters the operator of the four cells around it, so each
+// launch evaluates every face it needs once: the field(s) and (q, bt) are
+// staged in LDS on the tile grown by three; each thread evaluates its share
+// of the faces (the x-faces of the tile's rows, kTileX + 3 per row, then the
+// z-faces of its columns, TZ + 3 per column) into registers; once every
+// thread has read the staged values the faces are written over them; each
+// cell then combines its eight faces.
 
 template <typename T, int G, int R, bool ADJ>
 struct Lds4 {
     static constexpr int TZ = kWavesZ * R;
-    static constexpr int W = kTileX + 6, H = TZ + 6, N = W * H;       // tile grown by 3
-    static constexpr int P = (N + kBlock - 1) / kBlock;               // per-thread shares
-    // F[N] field (adjoint: lambda^t, then u^{t-1}), C[N][2] (q, bt)
-    static constexpr size_t bytes = (size_t)N * (G * (ADJ ? 2 : 1) + 2) * sizeof(T);
+    static constexpr int W = kTileX + 6, H = TZ + 6, N = W * H;        // tile grown by 3
+    static constexpr int P = (N + kBlock - 1) / kBlock;                // staging shares per thread
+    static constexpr int FXW = kTileX + 3;                             // x-faces per tile row
+    static constexpr int NFX = TZ * FXW, NF = NFX + (TZ + 3) * kTileX; // x-faces, then z-faces
+    static constexpr int PF = (NF + kBlock - 1) / kBlock;              // face shares per thread
+    // staging: field [N] (adjoint: w^t, then u^{t-1}) and (q, bt) [N][2];
+    // then, over it, the fluxes [NF] (adjoint: of w, then of u) and the
+    // adjoint's imaging products [NF]
+    static constexpr size_t stage = (size_t)N * (G * (ADJ ? 2 : 1) + 2) * sizeof(T);
+    static constexpr size_t face = (size_t)NF * (G * (ADJ ? 2 : 1) + (ADJ ? 1 : 0)) * sizeof(T);
+    static constexpr size_t bytes = stage > face ? stage : face;
 };
 
 // D v at a face from the four values around it (v_{j-1}, v_j, v_{j+1}, v_{j+2}).
@@ -1583,198 +1713,249 @@ __device__ __forceinline__ T div4(T fm3, T fm1, T fp1, T fp3)
     return fma(T(9) / T(8), fp1 - fm1, (T(-1) / T(24)) * (fp3 - fm3));
 }
 
-// Operator along one axis at LDS cell k (neighbour stride s) for every
-// transmit: L += 9/8 (F(k) - F(k-s)) - 1/24 (F(k+s) - F(k-2s)), F(m) the flux
-// through the face between cells m and m+s of the field V.
+// First of the four LDS cells that face f of a step's list differences, and
+// the stride along its axis.  The step updates a region of CW x RH cells
+// whose first cell sits at (OFF + 3, OFF + 3) of the staged layout (row width
+// W); its list holds the x-faces, CW + 3 per row and row by row (face i of a
+// row lies between the region's columns i - 3 and i - 2), then the z-faces,
+// RH + 3 per column and stored by face row (face row j lies between the
+// region's rows j - 3 and j - 2).
+template <int W, int CW, int RH, int OFF>
+__device__ __forceinline__ void face_cells(int f, int& k0, int& s)
+{
+    constexpr int FXW = CW + 3, NFX = RH * FXW;
+    if (f < NFX) {
+        const int r = f / FXW;
+        k0 = (r + 3 + OFF) * W + (f - r * FXW) + OFF;
+        s = 1;
+    } else {
+        const int h = f - NFX, j = h / CW;
+        k0 = (j + OFF) * W + (h - j * CW) + 3 + OFF;
+        s = W;
+    }
+}
+
+// Flux bt_f D u through a face (k0, s) for every transmit.
 template <typename T, int G>
-__device__ __forceinline__ void lap4_axis(const Vec<T, G>* V, const T* C, int k, int s, Vec<T, G>& L)
+__device__ __forceinline__ Vec<T, G> flux4(const Vec<T, G>* V, const T* C, int k0, int s)
 {
-    Vec<T, G> v[7];
-    T bt[5];
+    const Vec<T, G> a = V[k0], b = V[k0 + s], c = V[k0 + 2 * s], d = V[k0 + 3 * s];
+    const T bf = T(0.5) * (C[2 * (k0 + s) + 1] + C[2 * (k0 + 2 * s) + 1]);
+    Vec<T, G> r;
 #pragma unroll
-    for (int i = 0; i < 7; ++i) v[i] = V[k + (i - 3) * s];
-#pragma unroll
-    for (int i = 0; i < 5; ++i) bt[i] = C[2 * (k + (i - 2) * s) + 1];
-    const T hf = T(0.5);
-    const T b32 = hf * (bt[0] + bt[1]), b12 = hf * (bt[1] + bt[2]), p12 = hf * (bt[2] + bt[3]),
-            p32 = hf * (bt[3] + bt[4]);
+    for (int g = 0; g < G; ++g) r.v[g] = bf * d4<T>(a.v[g], b.v[g], c.v[g], d.v[g]);
+    return r;
+}
+
+// The adjoint's face values: the fluxes bt_f D w and bt_f D u (w = q lam^t,
+// u = u^{t-1}) for every transmit, and the imaging product sum_g D u D w.
+template <typename T, int G>
+__device__ __forceinline__ void flux4_adj(const Vec<T, G>* Wl, const Vec<T, G>* U, const T* C, int k0, int s,
+                                          Vec<T, G>& fw, Vec<T, G>& fu, T& pr)
+{
+#pragma clang fp contract(off)
+    const Vec<T, G> w0 = Wl[k0], w1 = Wl[k0 + s], w2 = Wl[k0 + 2 * s], w3 = Wl[k0 + 3 * s];
+    const Vec<T, G> u0 = U[k0], u1 = U[k0 + s], u2 = U[k0 + 2 * s], u3 = U[k0 + 3 * s];
+    const T bf = T(0.5) * (C[2 * (k0 + s) + 1] + C[2 * (k0 + 2 * s) + 1]);
+    pr = T(0);
 #pragma unroll
     for (int g = 0; g < G; ++g) {
-        const T fm3 = b32 * d4<T>(v[0].v[g], v[1].v[g], v[2].v[g], v[3].v[g]);
-        const T fm1 = b12 * d4<T>(v[1].v[g], v[2].v[g], v[3].v[g], v[4].v[g]);
-        const T fp1 = p12 * d4<T>(v[2].v[g], v[3].v[g], v[4].v[g], v[5].v[g]);
-        const T fp3 = p32 * d4<T>(v[3].v[g], v[4].v[g], v[5].v[g], v[6].v[g]);
-        L.v[g] += div4<T>(fm3, fm1, fp1, fp3);
+        const T dw = d4<T>(w0.v[g], w1.v[g], w2.v[g], w3.v[g]);
+        const T du = d4<T>(u0.v[g], u1.v[g], u2.v[g], u3.v[g]);
+        fw.v[g] = bf * dw;
+        fu.v[g] = bf * du;
+        pr = fma(du, dw, pr);
     }
 }
 
-// Adjoint work of one axis at LDS cell k (position i of n along the axis),
-// from one read of the seven w^t = q lambda^t and u^{t-1} values and five bt
-// around it: Lw += flux operator of w (the cell's q is applied by the
-// caller), Lu += operator of u, and the
-// imaging share sb += sum over the faces whose bt involve the cell of its
-// part of (D u)_f (D w)_f: half of each neighbouring face, the whole face
-// where the neighbour is a ghost repeating this cell, and the face between
-// the two ghosts beyond a border cell.
-template <typename T, int G, typename Acc>
-__device__ __forceinline__ void adj4_axis(const Vec<T, G>* Lm, const Vec<T, G>* U, const T* C, int k, int s, int i,
-                                          int n, Vec<T, G>& Lw, Vec<T, G>& Lu, Acc& sb)
+// Imaging share of a cell's bt along one axis (position i of n) from the
+// products at its four faces, p0 .. p3 at j - 3/2 .. j + 3/2: half of each
+// neighbouring face, the whole face where the neighbour is a ghost repeating
+// this cell, and the face between the two ghosts beyond a border cell.
+template <typename T>
+__device__ __forceinline__ T img4(T p0, T p1, T p2, T p3, int i, int n)
 {
-    Vec<T, G> l[7], u[7];
-    T bt[5];
-#pragma unroll
-    for (int j = 0; j < 7; ++j) {
-        l[j] = Lm[k + (j - 3) * s];
-        u[j] = U[k + (j - 3) * s];
-    }
-#pragma unroll
-    for (int j = 0; j < 5; ++j) bt[j] = C[2 * (k + (j - 2) * s) + 1];
+#pragma clang fp contract(off)
     const T hf = T(0.5);
-    const T b32 = hf * (bt[0] + bt[1]), b12 = hf * (bt[1] + bt[2]), p12 = hf * (bt[2] + bt[3]),
-            p32 = hf * (bt[3] + bt[4]);
-    const T wm = i == 0 ? T(1) : hf, wp = i == n - 1 ? T(1) : hf;
-    const T gm = i == 0 ? T(1) : T(0), gp = i == n - 1 ? T(1) : T(0);
+    T s = (i == 0 ? p1 : hf * p1) + (i == n - 1 ? p2 : hf * p2);
+    if (i == 0) s = s + p0;
+    if (i == n - 1) s = s + p3;
+    return s;
+}
+
+// Forward update (increment form) of the cell at (cx, cz) of a CW x RH
+// region from its eight fluxes in F (the region's face list): v^{n+1} into vv
+// (v^n given there), u^{n+1} returned.  Every fourth-order forward kernel
+// updates a cell through this function, so launches of one and of two steps
+// round a cell identically.
+template <typename T, int G, int CW, int RH>
+__device__ __forceinline__ Vec<T, G> cell4(const Vec<T, G>* F, int cx, int cz, T q, T e, const Vec<T, G>& u0,
+                                          Vec<T, G>& vv, int cell, const Src<T, G>& sc, bool near)
+{
+    constexpr int FXW = CW + 3, NFX = RH * FXW;
+    const int ax = cz * FXW + cx, az = NFX + cz * CW + cx;
+    const Vec<T, G> x0f = F[ax], x1f = F[ax + 1], x2f = F[ax + 2], x3f = F[ax + 3];
+    const Vec<T, G> z0f = F[az], z1f = F[az + CW], z2f = F[az + 2 * CW], z3f = F[az + 3 * CW];
+    T nb, c2;
+    damp_inc<T>(e, nb, c2);
+    Vec<T, G> r;
 #pragma unroll
     for (int g = 0; g < G; ++g) {
-        T w[7], v[7];
-#pragma unroll
-        for (int j = 0; j < 7; ++j) {
-            w[j] = l[j].v[g];
-            v[j] = u[j].v[g];
-        }
-        const T dw3 = d4<T>(w[0], w[1], w[2], w[3]), dw1 = d4<T>(w[1], w[2], w[3], w[4]);
-        const T ew1 = d4<T>(w[2], w[3], w[4], w[5]), ew3 = d4<T>(w[3], w[4], w[5], w[6]);
-        const T du3 = d4<T>(v[0], v[1], v[2], v[3]), du1 = d4<T>(v[1], v[2], v[3], v[4]);
-        const T eu1 = d4<T>(v[2], v[3], v[4], v[5]), eu3 = d4<T>(v[3], v[4], v[5], v[6]);
-        Lw.v[g] += div4<T>(b32 * dw3, b12 * dw1, p12 * ew1, p32 * ew3);
-        Lu.v[g] += div4<T>(b32 * du3, b12 * du1, p12 * eu1, p32 * eu3);
-        sb += Acc(wm * (du1 * dw1) + wp * (eu1 * ew1) + gm * (du3 * dw3) + gp * (eu3 * ew3));
+#pragma clang fp contract(off)
+        T Lu = div4<T>(x0f.v[g], x1f.v[g], x2f.v[g], x3f.v[g]);
+        Lu += div4<T>(z0f.v[g], z1f.v[g], z2f.v[g], z3f.v[g]);
+        vv.v[g] = fma(q, Lu, fma(nb, vv.v[g], c2 * u0.v[g]));
     }
+    if (near) add_src<T, G>(vv, cell, sc);
+#pragma unroll
+    for (int g = 0; g < G; ++g) r.v[g] = u0.v[g] + vv.v[g];
+    return r;
 }
 
-// Stage two fields (zero outside the grid) and (q, bt) at clamped positions
-// on the tile grown by three, all loads issued before the first LDS store.
-template <typename T, int G, typename Acc, int P, int W, int N>
-__device__ __forceinline__ void stage4x2(const Item<T, Acc>& it, const T* f1, const T* f2, int x0, int z0, int tid,
-                                         Vec<T, G>* F1, Vec<T, G>* F2, T* C)
+// Global loads of one tile of a one-step fourth-order launch, issued
+// together and held in registers until the LDS is free: the field(s) (zero
+// outside the grid) and (q, bt) at clamped positions on the tile grown by
+// three, and at the lane's R cells v^n (forward) or w^{t+1} and the two
+// imaging sums (adjoint), with the damping profile.
+template <typename T, int G, typename Acc, int R, bool ADJ>
+struct Load4 {
+    using L = Lds4<T, G, R, ADJ>;
+    Vec<T, G> a[L::P], b[ADJ ? L::P : 1];
+    T q[L::P], bt[L::P];
+    Vec<T, G> v[R];
+    Acc sK[R], sB[R];
+    T ez[R];
+    T ex;
+};
+
+template <typename T, int G, typename Acc, int R, bool ADJ>
+__device__ __forceinline__ void load4(const Item<T, Acc>& it, const Step& st, int tile_x, int tile_z,
+                                      Load4<T, G, Acc, R, ADJ>& ld)
 {
+    using L = Lds4<T, G, R, ADJ>;
     const int nx = it.nx, nz = it.nz;
-    Vec<T, G> a[P], b[P];
-    T qv[P], bv[P];
+    const int x0 = tile_x * kTileX, z0 = tile_z * L::TZ;
+    const int tid = threadIdx.y * kTileX + threadIdx.x;
+    const int ix = x0 + (int)threadIdx.x;
+    const T* f1;
+    const T* f2 = nullptr;
+    const T* pv;
+    if (ADJ) {
+        const int t = st.n;
+        f1 = it.lam + (int64_t)(t & (it.nlam - 1)) * it.plane;          // w^t
+        f2 = it.seg + (int64_t)kmod(it, t - 2) * it.plane;              // u^{t-1}
+        pv = it.lam + (int64_t)((t + 1) & (it.nlam - 1)) * it.plane;    // w^{t+1}
+    } else {
+        f1 = fwd_plane(it, st, st.n);                                   // u^n
+        pv = vel_in(it, st, st.n);                                      // v^n
+    }
 #pragma unroll
-    for (int i = 0; i < P; ++i) {
+    for (int i = 0; i < L::P; ++i) {
         const int c = tid + i * kBlock;
-        const int gx = x0 - 3 + c % W, gz = z0 - 3 + c / W;
-        const bool in = c < N && gx >= 0 && gx < nx && gz >= 0 && gz < nz;
+        const int gx = x0 - 3 + c % L::W, gz = z0 - 3 + c / L::W;
+        const bool in = c < L::N && gx >= 0 && gx < nx && gz >= 0 && gz < nz;
         const int cx = min(max(gx, 0), nx - 1), cz = min(max(gz, 0), nz - 1);
-        const int64_t xc = c < N ? (int64_t)cz * nx + cx : 0;
-        const int64_t xi = in ? (int64_t)gz * nx + gx : 0;
-        a[i] = vkeep<T, G>(in, vload<T, G>(f1, xi));
-        b[i] = vkeep<T, G>(in, vload<T, G>(f2, xi));
-        qv[i] = ldg(it.coef, 2 * xc);
-        bv[i] = ldg(it.coef, 2 * xc + 1);
+        const uint32_t xc = c < L::N ? (uint32_t)(cz * nx + cx) : 0u;
+        const uint32_t xi = in ? (uint32_t)(gz * nx + gx) : 0u;
+        ld.a[i] = vkeep<T, G>(in, vload32<T, G>(f1, xi));
+        if (ADJ) ld.b[i] = vkeep<T, G>(in, vload32<T, G>(f2, xi));
+        ld.q[i] = ldg32(it.coef, 2 * xc);
+        ld.bt[i] = ldg32(it.coef, 2 * xc + 1);
     }
 #pragma unroll
-    for (int i = 0; i < P; ++i) {
-        const int c = tid + i * kBlock;
-        if (c < N) {
-            F1[c] = a[i];
-            F2[c] = b[i];
-            C[2 * c] = qv[i];
-            C[2 * c + 1] = bv[i];
+    for (int k = 0; k < R; ++k) {
+        const int iz = z0 + (int)threadIdx.y * R + k;
+        const bool in = ix < nx && iz < nz;
+        const uint32_t x = in ? (uint32_t)(iz * nx + ix) : 0u;
+        ld.v[k] = vload32<T, G>(pv, x);
+        if (ADJ) {
+            ld.sK[k] = ldg32(it.acc, x);
+            ld.sB[k] = ldg32(it.acc + (int64_t)nx * nz, x);
         }
+        ld.ez[k] = ldg(it.ez, iz < nz ? iz : 0);
     }
+    ld.ex = ldg(it.ex, ix < nx ? ix : 0);
 }
 
-// Stage a field (zero outside the grid) and (q, bt) at clamped positions on
-// the tile grown by three.
-template <typename T, int G, typename Acc, int P, int W, int N>
-__device__ __forceinline__ void stage4(const Item<T, Acc>& it, const T* f, int x0, int z0, int tid,
-                                       Vec<T, G>* F, T* C)
+// The staged values into LDS: field(s) F1 (F2) and (q, bt) C.
+template <typename T, int G, typename Acc, int R, bool ADJ>
+__device__ __forceinline__ void commit4(const Load4<T, G, Acc, R, ADJ>& ld, Vec<T, G>* F1, Vec<T, G>* F2, T* C)
 {
-    const int nx = it.nx, nz = it.nz;
-    Vec<T, G> fv[P];
-    T qv[P], bv[P];
+    using L = Lds4<T, G, R, ADJ>;
+    const int tid = threadIdx.y * kTileX + threadIdx.x;
 #pragma unroll
-    for (int i = 0; i < P; ++i) {
+    for (int i = 0; i < L::P; ++i) {
         const int c = tid + i * kBlock;
-        const int gx = x0 - 3 + c % W, gz = z0 - 3 + c / W;
-        const bool in = c < N && gx >= 0 && gx < nx && gz >= 0 && gz < nz;
-        const int cx = min(max(gx, 0), nx - 1), cz = min(max(gz, 0), nz - 1);
-        const int64_t xc = c < N ? (int64_t)cz * nx + cx : 0;
-        fv[i] = vkeep<T, G>(in, vload<T, G>(f, in ? (int64_t)gz * nx + gx : 0));
-        qv[i] = ldg(it.coef, 2 * xc);
-        bv[i] = ldg(it.coef, 2 * xc + 1);
-    }
-#pragma unroll
-    for (int i = 0; i < P; ++i) {
-        const int c = tid + i * kBlock;
-        if (c < N) {
-            F[c] = fv[i];
-            C[2 * c] = qv[i];
-            C[2 * c + 1] = bv[i];
+        if (c < L::N) {
+            F1[c] = ld.a[i];
+            if (ADJ) F2[c] = ld.b[i];
+            C[2 * c] = ld.q[i];
+            C[2 * c + 1] = ld.bt[i];
         }
     }
 }
 
+// Forward step n of one tile from the staged values (committed to LDS and
+// made visible by the caller's barrier).
 template <typename T, int G, typename Acc, int R>
 __device__ void tile_forward4(const Item<T, Acc>& it, const Step& st, int tile_x, int tile_z, bool sample,
-                              unsigned char* smem)
+                              unsigned char* smem, const Load4<T, G, Acc, R, false>& ld)
 {
     using L = Lds4<T, G, R, false>;
     const int nx = it.nx, nz = it.nz, n = st.n;
-    Vec<T, G>* U = reinterpret_cast<Vec<T, G>*>(smem);
-    T* C = reinterpret_cast<T*>(U + L::N);
-    const T* cur = fwd_plane(it, st, n);
-    const T* vin = vel_in(it, st, n);
-    T* out = it.seg + (int64_t)(n % it.K) * it.plane;
+    const Vec<T, G>* U = reinterpret_cast<const Vec<T, G>*>(smem);
+    const T* C = reinterpret_cast<const T*>(U + L::N);
+    Vec<T, G>* F = reinterpret_cast<Vec<T, G>*>(smem);                  // fluxes, over the staging
+    T* out = it.seg + (int64_t)kmod(it, n) * it.plane;
     T* vout = vel_out(it, st, n + 1);
     T* ckv = ckpt_pair(it, st, n + 1);
     const Src<T, G> src = sources<T, G>(it, n);
     const Span rcv = sample ? span_of(it.tile_off, tile_z * it.tiles_x + tile_x) : Span{0, 0};
     const int x0 = tile_x * kTileX, z0 = tile_z * L::TZ;
+    // a source within the cells this launch updates (the tile)
+    const bool near = src_near<T, G, Acc>(src, it, x0, z0, 0, kTileX, 0, L::TZ);
     const int tid = threadIdx.y * kTileX + threadIdx.x;
-    const int ix = x0 + (int)threadIdx.x;
-    Vec<T, G> vt[R];
-    T ezd[R];
+    const int tx = (int)threadIdx.x, ix = x0 + tx;
+    // the lane's own u^n and q, then its faces, before the fluxes overwrite them
+    Vec<T, G> u0[R], vt[R];
+    T qc[R];
 #pragma unroll
     for (int k = 0; k < R; ++k) {
-        const int iz = z0 + (int)threadIdx.y * R + k;
-        const bool in = ix < nx && iz < nz;
-        vt[k] = vload<T, G>(vin, in ? (int64_t)iz * nx + ix : 0);
-        ezd[k] = ldg(it.ez, iz < nz ? iz : 0);
+        const int kk = ((int)threadIdx.y * R + k + 3) * L::W + tx + 3;
+        u0[k] = U[kk];
+        qc[k] = C[2 * kk];
+        vt[k] = ld.v[k];
     }
-    const T exd = ldg(it.ex, ix < nx ? ix : 0);
-    stage4<T, G, Acc, L::P, L::W, L::N>(it, cur, x0, z0, tid, U, C);
+    Vec<T, G> fl[L::PF];
+#pragma unroll
+    for (int i = 0; i < L::PF; ++i) {
+        const int f = tid + i * kBlock;
+        if (f < L::NF) {
+            int k0, s;
+            face_cells<L::W, kTileX, L::TZ, 0>(f, k0, s);
+            fl[i] = flux4<T, G>(U, C, k0, s);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < L::PF; ++i) {
+        const int f = tid + i * kBlock;
+        if (f < L::NF) F[f] = fl[i];
+    }
     __syncthreads();
     if (ix < nx) {
 #pragma unroll
         for (int k = 0; k < R; ++k) {
-            const int ez = (int)threadIdx.y * R + k, iz = z0 + ez;
+            const int z = (int)threadIdx.y * R + k, iz = z0 + z;
             if (iz < nz) {
-                const int kk = (ez + 3) * L::W + threadIdx.x + 3;
-                const int64_t x = (int64_t)iz * nx + ix;
-                Vec<T, G> Lu = vzero<T, G>();
-                lap4_axis<T, G>(U, C, kk, 1, Lu);
-                lap4_axis<T, G>(U, C, kk, L::W, Lu);
-                T nb, c2;
-                damp_inc<T>(exd + ezd[k], nb, c2);
-                const T q = C[2 * kk];
-                const Vec<T, G> u0 = U[kk];
-                Vec<T, G> r, rv;
-#pragma unroll
-                for (int g = 0; g < G; ++g) {
-#pragma clang fp contract(off)
-                    T v = fma(q, Lu.v[g], fma(nb, vt[k].v[g], c2 * u0.v[g]));
-                    if ((int)x == src.cell[g]) v += src.w[g];
-                    rv.v[g] = v;
-                    r.v[g] = u0.v[g] + v;
-                }
-                vstore<T, G>(out, x, r);
-                vstore<T, G>(vout, x, rv);
+                const uint32_t x = (uint32_t)(iz * nx + ix);
+                const Vec<T, G> r =
+                    cell4<T, G, kTileX, L::TZ>(F, tx, z, qc[k], ld.ex + ld.ez[k], u0[k], vt[k], (int)x, src, near);
+                vstore32<T, G>(out, x, r);
+                vstore32<T, G>(vout, x, vt[k]);
                 if (ckv) {
-                    vstore<T, G>(ckv, x, rv);
-                    vstore<T, G>(ckv + it.plane, x, r);
+                    vstore32<T, G>(ckv, x, vt[k]);
+                    vstore32<T, G>(ckv + it.plane, x, r);
                 }
             }
         }
@@ -1782,8 +1963,11 @@ __device__ void tile_forward4(const Item<T, Acc>& it, const Step& st, int tile_x
     sample_tile(it, rcv, n, out, (const T*)nullptr);
 }
 
+// Adjoint step t of one tile, with the imaging of (w^t, u^{t-1}), from the
+// staged values (committed and made visible by the caller).
 template <typename T, int G, typename Acc, int R>
-__device__ void tile_adjoint4(const Item<T, Acc>& it, const Step& st, int tile_x, int tile_z, unsigned char* smem)
+__device__ void tile_adjoint4(const Item<T, Acc>& it, const Step& st, int tile_x, int tile_z, unsigned char* smem,
+                              const Load4<T, G, Acc, R, true>& ld)
 {
     using L = Lds4<T, G, R, true>;
     const int nx = it.nx, nz = it.nz, t = st.n;
@@ -1791,67 +1975,357 @@ __device__ void tile_adjoint4(const Item<T, Acc>& it, const Step& st, int tile_x
     // the planes hold w = q lam, as for the second-order operator: w^{t-1} =
     // a w^t + b w^{t+1} + q (flux terms of w), and the kappa term w^t L u is q
     // times the lambda one (undone when the gradient is formed)
-    Vec<T, G>* Lm = reinterpret_cast<Vec<T, G>*>(smem);                 // w^t
-    Vec<T, G>* U = Lm + L::N;                                           // u^{t-1}
-    T* C = reinterpret_cast<T*>(U + L::N);
-    const T* cur = it.lam + (int64_t)(t % it.nlam) * P;                 // w^t
-    const T* p1 = it.lam + (int64_t)((t + 1) % it.nlam) * P;            // w^{t+1}
-    T* out = it.lam + (int64_t)((t - 1) % it.nlam) * P;                 // w^{t-1}
-    const T* um = it.seg + (int64_t)((t - 2) % it.K) * P;               // u^{t-1}
+    const Vec<T, G>* Lm = reinterpret_cast<const Vec<T, G>*>(smem);     // w^t
+    const Vec<T, G>* U = Lm + L::N;                                     // u^{t-1}
+    const T* C = reinterpret_cast<const T*>(U + L::N);
+    Vec<T, G>* FW = reinterpret_cast<Vec<T, G>*>(smem);                 // faces, over the staging
+    Vec<T, G>* FU = FW + L::NF;
+    T* FP = reinterpret_cast<T*>(FU + L::NF);
+    T* out = it.lam + (int64_t)((t - 1) & (it.nlam - 1)) * P;           // w^{t-1}
     Acc* accK = it.acc;
     Acc* accB = it.acc + ncell;
-    const int tile = tile_z * it.tiles_x + tile_x;
-    const Span rcv = span_of(it.tile_off, tile);
+    const Span rcv = span_of(it.tile_off, tile_z * it.tiles_x + tile_x);
     const int x0 = tile_x * kTileX, z0 = tile_z * L::TZ;
     const int tid = threadIdx.y * kTileX + threadIdx.x;
-    const int ix = x0 + (int)threadIdx.x;
-    Vec<T, G> lp[R];
-    Acc sK[R], sB[R];
-    T ezd[R];
+    const int tx = (int)threadIdx.x, ix = x0 + tx;
+    Vec<T, G> w0[R];
+    T qc[R];
 #pragma unroll
     for (int k = 0; k < R; ++k) {
-        const int iz = z0 + (int)threadIdx.y * R + k;
-        const bool in = ix < nx && iz < nz;
-        const int64_t x = in ? (int64_t)iz * nx + ix : 0;
-        lp[k] = vload<T, G>(p1, x);
-        sK[k] = ldg(accK, x);
-        sB[k] = ldg(accB, x);
-        ezd[k] = ldg(it.ez, iz < nz ? iz : 0);
+        const int kk = ((int)threadIdx.y * R + k + 3) * L::W + tx + 3;
+        w0[k] = Lm[kk];
+        qc[k] = C[2 * kk];
     }
-    const T exd = ldg(it.ex, ix < nx ? ix : 0);
-    stage4x2<T, G, Acc, L::P, L::W, L::N>(it, cur, um, x0, z0, tid, Lm, U, C);
+    Vec<T, G> fw[L::PF], fu[L::PF];
+    T pr[L::PF];
+#pragma unroll
+    for (int i = 0; i < L::PF; ++i) {
+        const int f = tid + i * kBlock;
+        if (f < L::NF) {
+            int k0, s;
+            face_cells<L::W, kTileX, L::TZ, 0>(f, k0, s);
+            flux4_adj<T, G>(Lm, U, C, k0, s, fw[i], fu[i], pr[i]);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < L::PF; ++i) {
+        const int f = tid + i * kBlock;
+        if (f < L::NF) {
+            FW[f] = fw[i];
+            FU[f] = fu[i];
+            FP[f] = pr[i];
+        }
+    }
     __syncthreads();
     if (ix < nx) {
 #pragma unroll
         for (int k = 0; k < R; ++k) {
-            const int ez = (int)threadIdx.y * R + k, iz = z0 + ez;
+            const int z = (int)threadIdx.y * R + k, iz = z0 + z;
             if (iz < nz) {
-                const int kk = (ez + 3) * L::W + threadIdx.x + 3;
-                const int64_t x = (int64_t)iz * nx + ix;
-                Vec<T, G> Lw = vzero<T, G>(), Lu = vzero<T, G>();
-                Acc sb = Acc(0);
-                adj4_axis<T, G, Acc>(Lm, U, C, kk, 1, ix, nx, Lw, Lu, sb);
-                adj4_axis<T, G, Acc>(Lm, U, C, kk, L::W, iz, nz, Lw, Lu, sb);
+                const int ax = z * L::FXW + tx, az = L::NFX + z * kTileX + tx;
                 T a, b;
-                damp_coeffs<T>(exd + ezd[k], a, b);
-                const Vec<T, G> l0 = Lm[kk];
-                const T qc = C[2 * kk];
+                damp_coeffs<T>(ld.ex + ld.ez[k], a, b);
+                const uint32_t x = (uint32_t)(iz * nx + ix);
                 Vec<T, G> r;
                 Acc sk = Acc(0);
+                {
+                    const Vec<T, G> f0 = FW[ax], f1 = FW[ax + 1], f2 = FW[ax + 2], f3 = FW[ax + 3];
+                    const Vec<T, G> h0 = FW[az], h1 = FW[az + kTileX], h2 = FW[az + 2 * kTileX],
+                                    h3 = FW[az + 3 * kTileX];
 #pragma unroll
-                for (int g = 0; g < G; ++g) {
+                    for (int g = 0; g < G; ++g) {
 #pragma clang fp contract(off)
-                    r.v[g] = fma(a, l0.v[g], fma(b, lp[k].v[g], qc * Lw.v[g]));
-                    sk += Acc(l0.v[g] * Lu.v[g]);
+                        T Lw = div4<T>(f0.v[g], f1.v[g], f2.v[g], f3.v[g]);
+                        Lw += div4<T>(h0.v[g], h1.v[g], h2.v[g], h3.v[g]);
+                        r.v[g] = fma(a, w0[k].v[g], fma(b, ld.v[k].v[g], qc[k] * Lw));
+                    }
                 }
-                vstore<T, G>(out, x, r);
-                stg(accK, x, sK[k] + sk);
-                stg(accB, x, sB[k] + sb);
+                {
+                    const Vec<T, G> f0 = FU[ax], f1 = FU[ax + 1], f2 = FU[ax + 2], f3 = FU[ax + 3];
+                    const Vec<T, G> h0 = FU[az], h1 = FU[az + kTileX], h2 = FU[az + 2 * kTileX],
+                                    h3 = FU[az + 3 * kTileX];
+#pragma unroll
+                    for (int g = 0; g < G; ++g) {
+#pragma clang fp contract(off)
+                        T Lu = div4<T>(f0.v[g], f1.v[g], f2.v[g], f3.v[g]);
+                        Lu += div4<T>(h0.v[g], h1.v[g], h2.v[g], h3.v[g]);
+                        sk += Acc(w0[k].v[g] * Lu);
+                    }
+                }
+                const Acc sb = Acc(img4<T>(FP[ax], FP[ax + 1], FP[ax + 2], FP[ax + 3], ix, nx)) +
+                               Acc(img4<T>(FP[az], FP[az + kTileX], FP[az + 2 * kTileX], FP[az + 3 * kTileX], iz, nz));
+                vstore32<T, G>(out, x, r);
+                stg32(accK, x, ld.sK[k] + sk);
+                stg32(accB, x, ld.sB[k] + sb);
             }
         }
     }
     // adjoint source of w^{t-1}: q times sample t-2
     inject_tile<true, G>(it, rcv, t - 2, out);
+}
+
+// Two fourth-order forward steps per launch.  u^n and (q, bt) are staged on
+// the tile grown by six; step n runs on the tile grown by three (whose faces
+// read three cells further out), step n+1 on the tile.  Each lane keeps v in
+// registers for its R tile cells and for its share of the ring between the
+// tile and the tile grown by three, so v is read once per launch; u^{n+1}
+// goes back into the staged layout (zero outside the grid) for step n+1.
+template <typename T, int G, int R>
+struct Lds4x2 {
+    static constexpr int TZ = kWavesZ * R;
+    static constexpr int W = kTileX + 12, H = TZ + 12, N = W * H;        // tile grown by 6
+    static constexpr int P = (N + kBlock - 1) / kBlock;                 // staging shares per thread
+    static constexpr int CW1 = kTileX + 6, RH1 = TZ + 6;                 // step n: tile grown by 3
+    static constexpr int NR = CW1 * RH1 - kTileX * TZ;                   // its ring around the tile
+    static constexpr int PR = (NR + kBlock - 1) / kBlock;               // ring cells per thread
+    static constexpr int NF1 = RH1 * (CW1 + 3) + (RH1 + 3) * CW1;        // faces of step n
+    static constexpr int NF2 = TZ * (kTileX + 3) + (TZ + 3) * kTileX;    // faces of step n+1
+    static constexpr int PF1 = (NF1 + kBlock - 1) / kBlock, PF2 = (NF2 + kBlock - 1) / kBlock;
+    // one region holding in turn u^n [N], the fluxes of step n [NF1], u^{n+1}
+    // [N] and the fluxes of step n+1 [NF2]; then (q, bt) [N][2]
+    static constexpr size_t field = (size_t)(N > NF1 ? N : NF1) * G * sizeof(T);
+    static constexpr size_t bytes = field + (size_t)N * 2 * sizeof(T);
+};
+
+// Cell c of the ring between the tile (kTileX x TZ) and the tile grown by
+// three, tile-relative: the three rows above, the three below (full width),
+// then the three columns left and right of the tile's rows.
+template <int TZ>
+__device__ __forceinline__ void ring4_cell(int c, int& x, int& z)
+{
+    constexpr int WR = kTileX + 6, TB = 3 * WR;
+    if (c < TB) {
+        z = c / WR - 3;
+        x = c % WR - 3;
+    } else if (c < 2 * TB) {
+        c -= TB;
+        z = TZ + c / WR;
+        x = c % WR - 3;
+    } else if (c < 2 * TB + 3 * TZ) {
+        c -= 2 * TB;
+        z = c / 3;
+        x = c % 3 - 3;
+    } else {
+        c -= 2 * TB + 3 * TZ;
+        z = c / 3;
+        x = kTileX + c % 3;
+    }
+}
+
+template <typename T, int G, typename Acc, int R>
+__device__ void tile_forward4x2(const Item<T, Acc>& it, const Step& st, int tile_x, int tile_z, bool sample,
+                                unsigned char* smem)
+{
+    using L = Lds4x2<T, G, R>;
+    constexpr int W = L::W;
+    const int nx = it.nx, nz = it.nz, n = st.n;
+    Vec<T, G>* U = reinterpret_cast<Vec<T, G>*>(smem);       // u^n, fluxes, u^{n+1}, fluxes
+    T* C = reinterpret_cast<T*>(smem + L::field);             // (q, bt) on the tile grown by 6
+    const T* cur = fwd_plane(it, st, n);
+    const T* vin = vel_in(it, st, n);
+    T* out1 = it.seg + (int64_t)kmod(it, n) * it.plane;
+    T* out2 = it.seg + (int64_t)kmod(it, n + 1) * it.plane;
+    T* vout = vel_out(it, st, n + 2);
+    T* ck1 = ckpt_pair(it, st, n + 1);
+    T* ck2 = ckpt_pair(it, st, n + 2);
+    // u^{n+1} is stored only where the adjoint will read it
+    const bool keep1 = st.phase != kFwd || n + 1 >= it.keep_from;
+    const Src<T, G> s1 = sources<T, G>(it, n);
+    const Src<T, G> s2 = sources<T, G>(it, n + 1);
+    const Span rcv = sample ? span_of(it.tile_off, tile_z * it.tiles_x + tile_x) : Span{0, 0};
+    const int x0 = tile_x * kTileX, z0 = tile_z * L::TZ;
+    // a source within the cells this launch updates (step n on the tile grown by three)
+    const bool near = src_near<T, G, Acc>(s1, it, x0, z0, -3, kTileX + 3, -3, L::TZ + 3);
+    const int tid = threadIdx.y * kTileX + threadIdx.x;
+    const int tx = (int)threadIdx.x, ix = x0 + tx;
+
+    // this lane's ring cells (tile-relative), each in the grid or not
+    int rx[L::PR], rz[L::PR];
+    bool rin[L::PR];
+#pragma unroll
+    for (int i = 0; i < L::PR; ++i) {
+        const int c = tid + i * kBlock;
+        ring4_cell<L::TZ>(c, rx[i], rz[i]);
+        const int gx = x0 + rx[i], gz = z0 + rz[i];
+        rin[i] = c < L::NR && gx >= 0 && gx < nx && gz >= 0 && gz < nz;
+    }
+
+    // one burst: u^n (zero outside the grid) and (q, bt) at clamped
+    // positions on the tile grown by 6; v^n and e = (D_x + D_z) dt at the
+    // lane's tile and ring cells
+    Vec<T, G> fv[L::P];
+    T qv[L::P], bv[L::P];
+#pragma unroll
+    for (int i = 0; i < L::P; ++i) {
+        const int c = tid + i * kBlock;
+        const int gx = x0 - 6 + c % W, gz = z0 - 6 + c / W;
+        const bool in = c < L::N && gx >= 0 && gx < nx && gz >= 0 && gz < nz;
+        const int cx = min(max(gx, 0), nx - 1), cz = min(max(gz, 0), nz - 1);
+        const uint32_t xc = c < L::N ? (uint32_t)(cz * nx + cx) : 0u;
+        fv[i] = vkeep<T, G>(in, vload32<T, G>(cur, in ? (uint32_t)(gz * nx + gx) : 0u));
+        qv[i] = ldg32(it.coef, 2 * xc);
+        bv[i] = ldg32(it.coef, 2 * xc + 1);
+    }
+    Vec<T, G> vt[R], vr[L::PR];
+    T et[R], er[L::PR];
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        const int iz = z0 + (int)threadIdx.y * R + k;
+        const bool in = ix < nx && iz < nz;
+        vt[k] = vload32<T, G>(vin, in ? (uint32_t)(iz * nx + ix) : 0u);
+        et[k] = ldg(it.ex, ix < nx ? ix : 0) + ldg(it.ez, iz < nz ? iz : 0);
+    }
+#pragma unroll
+    for (int i = 0; i < L::PR; ++i) {
+        const int gx = x0 + rx[i], gz = z0 + rz[i];
+        vr[i] = vload32<T, G>(vin, rin[i] ? (uint32_t)(gz * nx + gx) : 0u);
+        er[i] = ldg(it.ex, rin[i] ? gx : 0) + ldg(it.ez, rin[i] ? gz : 0);
+    }
+#pragma unroll
+    for (int i = 0; i < L::P; ++i) {
+        const int c = tid + i * kBlock;
+        if (c < L::N) {
+            U[c] = fv[i];
+            C[2 * c] = qv[i];
+            C[2 * c + 1] = bv[i];
+        }
+    }
+    __syncthreads();
+
+    // the lane's own u^n and q, then the fluxes of step n, before they
+    // overwrite u^n
+    Vec<T, G> ut[R], ur[L::PR];
+    T qt[R], qr[L::PR];
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        const int kk = ((int)threadIdx.y * R + k + 6) * W + tx + 6;
+        ut[k] = U[kk];
+        qt[k] = C[2 * kk];
+    }
+#pragma unroll
+    for (int i = 0; i < L::PR; ++i) {
+        const int kk = tid + i * kBlock < L::NR ? (rz[i] + 6) * W + rx[i] + 6 : 0;
+        ur[i] = U[kk];
+        qr[i] = C[2 * kk];
+    }
+    {
+        Vec<T, G> fl[L::PF1];
+#pragma unroll
+        for (int i = 0; i < L::PF1; ++i) {
+            const int f = tid + i * kBlock;
+            if (f < L::NF1) {
+                int k0, s;
+                face_cells<W, L::CW1, L::RH1, 0>(f, k0, s);
+                fl[i] = flux4<T, G>(U, C, k0, s);
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < L::PF1; ++i) {
+            const int f = tid + i * kBlock;
+            if (f < L::NF1) U[f] = fl[i];
+        }
+    }
+    __syncthreads();
+
+    // step n on the tile grown by three; outside the grid u stays zero
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        const int z = (int)threadIdx.y * R + k, iz = z0 + z;
+        if (ix < nx && iz < nz) {
+            const uint32_t x = (uint32_t)(iz * nx + ix);
+            ut[k] = cell4<T, G, L::CW1, L::RH1>(U, tx + 3, z + 3, qt[k], et[k], ut[k], vt[k], (int)x, s1, near);
+            if (keep1) vstore32<T, G>(out1, x, ut[k]);
+            if (ck1) {
+                vstore32<T, G>(ck1, x, vt[k]);
+                vstore32<T, G>(ck1 + it.plane, x, ut[k]);
+            }
+        } else {
+            ut[k] = vzero<T, G>();
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < L::PR; ++i) {
+        if (rin[i]) {
+            const int cell = (z0 + rz[i]) * nx + x0 + rx[i];
+            ur[i] = cell4<T, G, L::CW1, L::RH1>(U, rx[i] + 3, rz[i] + 3, qr[i], er[i], ur[i], vr[i], cell, s1, near);
+        } else {
+            ur[i] = vzero<T, G>();
+        }
+    }
+    __syncthreads();
+    // u^{n+1} over the fluxes, in the staged layout
+#pragma unroll
+    for (int k = 0; k < R; ++k) U[((int)threadIdx.y * R + k + 6) * W + tx + 6] = ut[k];
+#pragma unroll
+    for (int i = 0; i < L::PR; ++i)
+        if (tid + i * kBlock < L::NR) U[(rz[i] + 6) * W + rx[i] + 6] = ur[i];
+    __syncthreads();
+    if (rcv.e1 > rcv.e0) sample_lds<T, G, 6>(it, rcv, n, U, W, x0, z0);
+
+    // the fluxes of step n+1, then step n+1 on the tile
+    {
+        Vec<T, G> fl[L::PF2];
+#pragma unroll
+        for (int i = 0; i < L::PF2; ++i) {
+            const int f = tid + i * kBlock;
+            if (f < L::NF2) {
+                int k0, s;
+                face_cells<W, kTileX, L::TZ, 3>(f, k0, s);
+                fl[i] = flux4<T, G>(U, C, k0, s);
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < L::PF2; ++i) {
+            const int f = tid + i * kBlock;
+            if (f < L::NF2) U[f] = fl[i];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        const int z = (int)threadIdx.y * R + k, iz = z0 + z;
+        if (ix < nx && iz < nz) {
+            const uint32_t x = (uint32_t)(iz * nx + ix);
+            const Vec<T, G> r = cell4<T, G, kTileX, L::TZ>(U, tx, z, qt[k], et[k], ut[k], vt[k], (int)x, s2, near);
+            vstore32<T, G>(out2, x, r);
+            vstore32<T, G>(vout, x, vt[k]);
+            if (ck2) {
+                vstore32<T, G>(ck2, x, vt[k]);
+                vstore32<T, G>(ck2 + it.plane, x, r);
+            }
+        }
+    }
+    // trace d[n+1] from the stored u^{n+2}
+    if (rcv.e1 > rcv.e0) {
+        __syncthreads();
+        for (int e = rcv.e0 + tid; e < rcv.e1; e += kBlock) {
+            const Entry en = ld_entry(it.entries, e);
+            stg(it.traces, en.trace_off + (int64_t)(n + 1) * it.n_rcv, ldg(out2, en.slot));
+        }
+    }
+}
+
+// One-step fourth-order launches: one tile per workgroup; its global loads
+// are issued together (load4), then written to LDS (commit4).
+template <typename T, int G, typename Acc, int R, bool ADJ>
+__device__ __forceinline__ void one_tile4(const Item<T, Acc>& it, const Step& st, int tile_x, int tile_z,
+                                          unsigned char* smem)
+{
+    using L = Lds4<T, G, R, ADJ>;
+    Vec<T, G>* F1 = reinterpret_cast<Vec<T, G>*>(smem);
+    Vec<T, G>* F2 = F1 + L::N;
+    T* C = reinterpret_cast<T*>(F1 + (ADJ ? 2 : 1) * L::N);
+    Load4<T, G, Acc, R, ADJ> ld;
+    load4<T, G, Acc, R, ADJ>(it, st, tile_x, tile_z, ld);
+    commit4<T, G, Acc, R, ADJ>(ld, F1, F2, C);
+    __syncthreads();
+    if constexpr (ADJ)
+        tile_adjoint4<T, G, Acc, R>(it, st, tile_x, tile_z, smem, ld);
+    else
+        tile_forward4<T, G, Acc, R>(it, st, tile_x, tile_z, st.phase == kFwd && it.sample, smem, ld);
 }
 
 template <typename T, int G, typename Acc, int R>
@@ -1863,8 +2337,22 @@ __global__ __launch_bounds__(kBlock) void fwd4_kernel(const Item<T, Acc>* __rest
     if (bt.x < 0) return;
     const Item<T, Acc>& it = items[bt.x];
     const Step st = item_step(it, s, mode);
-    if (st.phase != kFwd && st.phase != kRecomp) return;
-    tile_forward4<T, G, Acc, R>(it, st, bt.y % it.tiles_x, bt.y / it.tiles_x, st.phase == kFwd && it.sample, smem);
+    if ((st.phase != kFwd && st.phase != kRecomp) || st.count != 1) return;
+    const int tz = quo(bt.y, it.dtx);
+    one_tile4<T, G, Acc, R, false>(it, st, bt.y - tz * it.tiles_x, tz, smem);
+}
+
+template <typename T, int G, typename Acc, int R>
+__global__ __launch_bounds__(kBlock) void fwd4x2_kernel(const Item<T, Acc>* __restrict__ items,
+                                                         const int2* __restrict__ blocks, int s, int mode)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int2 bt = blocks[blockIdx.x];
+    if (bt.x < 0) return;
+    const Item<T, Acc>& it = items[bt.x];
+    const Step st = item_step(it, s, mode);
+    if ((st.phase != kFwd && st.phase != kRecomp) || st.count != 2) return;
+    tile_forward4x2<T, G, Acc, R>(it, st, bt.y - quo(bt.y, it.dtx) * it.tiles_x, quo(bt.y, it.dtx), st.phase == kFwd && it.sample, smem);
 }
 
 template <typename T, int G, typename Acc, int R>
@@ -1877,7 +2365,8 @@ __global__ __launch_bounds__(kBlock) void adj4_kernel(const Item<T, Acc>* __rest
     const Item<T, Acc>& it = items[bt.x];
     const Step st = item_step(it, s, mode);
     if (st.phase != kAdj) return;
-    tile_adjoint4<T, G, Acc, R>(it, st, bt.y % it.tiles_x, bt.y / it.tiles_x, smem);
+    const int tz = quo(bt.y, it.dtx);
+    one_tile4<T, G, Acc, R, true>(it, st, bt.y - tz * it.tiles_x, tz, smem);
 }
 
 // ---------------------------------------------------------------- persistent form
@@ -1947,7 +2436,7 @@ __global__ __launch_bounds__(kBlock) void persistent_kernel(const Item<T, Acc>* 
             if (bt.x >= 0) {
                 const Item<T, Acc>& it = items[bt.x];
                 const Step st = item_step(it, s, mode);
-                const int tx = bt.y % it.tiles_x, tz = bt.y / it.tiles_x;
+                const int tz = quo(bt.y, it.dtx), tx = bt.y - tz * it.tiles_x;
                 if (st.phase == kFwd || st.phase == kRecomp) {
                     const bool smp = st.phase == kFwd && it.sample;
                     if (st.count == 2) tile_forward2<T, G, Acc, R, 1>(it, st, tx, tz, smp, smem);

@@ -224,16 +224,20 @@ void launch2(int kind, dim3 grid, hipStream_t st, const Item<T, Acc>* it, const 
         hipLaunchKernelGGL((adj2_kernel<T, G, Acc, R>), grid, blk, lds_a, st, it, blocks, s, mode);
 }
 
-// Fourth-order one-step launches (kind 0 forward, 2 adjoint), R = 1, 2, 4.
+// Fourth-order launches (kind 0 one forward step, 1 two forward steps, 2
+// one adjoint step), R = 1, 2, 4.
 template <typename T, typename Acc, int G, int R>
 void launch4(int kind, dim3 grid, hipStream_t st, const Item<T, Acc>* it, const int2* blocks, int s, int mode)
 {
     const dim3 blk(kTileX, kWavesZ);
     constexpr size_t lds_f = Lds4<T, G, R, false>::bytes;
+    constexpr size_t lds_2 = Lds4x2<T, G, R>::bytes;
     constexpr size_t lds_a = Lds4<T, G, R, true>::bytes;
     if (kind == 0)
         hipLaunchKernelGGL((fwd4_kernel<T, G, Acc, R>), grid, blk, lds_f, st, it, blocks, s, mode);
-    else
+    else if (kind == 1)
+        hipLaunchKernelGGL((fwd4x2_kernel<T, G, Acc, R>), grid, blk, lds_2, st, it, blocks, s, mode);
+    else if constexpr (lds_a <= kLdsBytes)     // plans whose adjoint tile exceeds the LDS are refused
         hipLaunchKernelGGL((adj4_kernel<T, G, Acc, R>), grid, blk, lds_a, st, it, blocks, s, mode);
 }
 
@@ -282,8 +286,15 @@ hipError_t allow_lds4()
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&fwd4_kernel<T, G, Acc, R>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)Lds4<T, G, R, false>::bytes);
     if (e != hipSuccess) return e;
-    return hipFuncSetAttribute(reinterpret_cast<const void*>(&adj4_kernel<T, G, Acc, R>),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)Lds4<T, G, R, true>::bytes);
+    if (Lds4x2<T, G, R>::bytes <= kLdsBytes) {
+        e = hipFuncSetAttribute(reinterpret_cast<const void*>(&fwd4x2_kernel<T, G, Acc, R>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)Lds4x2<T, G, R>::bytes);
+        if (e != hipSuccess) return e;
+    }
+    if constexpr (Lds4<T, G, R, true>::bytes <= kLdsBytes)
+        return hipFuncSetAttribute(reinterpret_cast<const void*>(&adj4_kernel<T, G, Acc, R>),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)Lds4<T, G, R, true>::bytes);
+    return hipSuccess;
 }
 
 template <typename T, typename Acc, int G>
@@ -314,7 +325,8 @@ size_t lds_of(int kind, int rows, int order)
 {
     auto byR = [&](auto r) -> size_t {
         constexpr int R = decltype(r)::value;
-        if (order == 4) return kind == 0 ? Lds4<T, G, R, false>::bytes : Lds4<T, G, R, true>::bytes;
+        if (order == 4)
+            return kind == 0 ? Lds4<T, G, R, false>::bytes : kind == 1 ? Lds4x2<T, G, R>::bytes : Lds4<T, G, R, true>::bytes;
         if (kind == 1) return Lds2<T, G, R, false>::bytes;
         if (kind == 3) return Lds2<T, G, R, true>::bytes;
         return Lds3<T, G, R>::bytes;
@@ -324,6 +336,34 @@ size_t lds_of(int kind, int rows, int order)
     if (rows == 2) return byR(std::integral_constant<int, 2>());
     return byR(std::integral_constant<int, 4>());
 }
+
+// LDS of the fourth-order launches of a plan with this dtype, G, rows and
+// forward steps per launch (the largest layout the plan launches).
+size_t lds4_need(fwi_dtype dtype, int G, int rows, int S)
+{
+    auto byR = [&](auto t, auto g) -> size_t {
+        using T = decltype(t);
+        constexpr int GG = decltype(g)::value;
+        auto one = [&](auto r) -> size_t {
+            constexpr int R = decltype(r)::value;
+            const size_t one = std::max(Lds4<T, GG, R, false>::bytes, Lds4<T, GG, R, true>::bytes);
+            return S >= 2 ? std::max(one, Lds4x2<T, GG, R>::bytes) : one;
+        };
+        if (rows == 1) return one(std::integral_constant<int, 1>());
+        if (rows == 2) return one(std::integral_constant<int, 2>());
+        return one(std::integral_constant<int, 4>());
+    };
+    auto byG = [&](auto t) -> size_t {
+        if (G == 1) return byR(t, std::integral_constant<int, 1>());
+        if (G == 2) return byR(t, std::integral_constant<int, 2>());
+        return byR(t, std::integral_constant<int, 4>());
+    };
+    return dtype == FWI_F64 ? byG(double()) : byG(float());
+}
+
+// Adjoint steps fused per launch: up to two for the second-order operator,
+// one for the fourth-order operator.
+int adjoint_steps(int order, int S) { return order == 4 ? 1 : std::min(S, 2); }
 
 size_t step_lds(const fwi_plan* p, int kind)
 {
@@ -339,7 +379,7 @@ size_t step_lds(const fwi_plan* p, int kind)
 void step(fwi_plan* p, int kind, dim3 grid, hipStream_t st, const int2* blocks, int s, int mode)
 {
     if (recording()) {
-        const int id = p->order == 4 ? (kind == 0 ? FWI_K_FWD4 : FWI_K_ADJ4) : kind;
+        const int id = p->order == 4 ? (kind == 0 ? FWI_K_FWD4 : kind == 1 ? FWI_K_FWD4X2 : FWI_K_ADJ4) : kind;
         record(id, grid, dim3(kTileX, kWavesZ), step_lds(p, kind));
         return;
     }
@@ -543,7 +583,8 @@ static fwi_status create_impl(fwi_plan* p, fwi_dtype dtype, const fwi_grid* grid
                                         "not persistent, without graph, not forward-only");
     if (o.order == 4) {
         if (o.persistent) return fail(p, FWI_ERR_INVALID, "the fourth-order operator has no persistent form");
-        if (o.steps_per_launch >= 2) return fail(p, FWI_ERR_INVALID, "the fourth-order operator runs one step per launch");
+        if (o.steps_per_launch >= 3)
+            return fail(p, FWI_ERR_INVALID, "the fourth-order operator runs one or two forward steps per launch");
         if (o.rows != 0 && o.rows != 1 && o.rows != 2 && o.rows != 4)
             return fail(p, FWI_ERR_INVALID, "the fourth-order operator needs rows of 1, 2 or 4");
     }
@@ -569,11 +610,11 @@ static fwi_status create_impl(fwi_plan* p, fwi_dtype dtype, const fwi_grid* grid
     };
     p->order = o.order == 4 ? 4 : 2;
     if (p->order == 4) {
-        p->S = 1;
-        p->rows = o.rows ? o.rows : 2;
-        const size_t ts = dtype == FWI_F64 ? 8 : 4;
-        const size_t n4 = (size_t)(kTileX + 6) * (kWavesZ * p->rows + 6);
-        if (n4 * (2 * p->G + 2) * ts > kLdsBytes)
+        // one forward step per launch unless two are asked for (plain mode:
+        // one); the adjoint runs one step per launch
+        p->S = (o.steps_per_launch == 2 && o.mode != FWI_PLAIN) ? 2 : 1;
+        p->rows = o.rows ? o.rows : 1;
+        if (lds4_need(dtype, p->G, p->rows, p->S) > kLdsBytes)
             return fail(p, FWI_ERR_INVALID, "the fourth-order tile of these rows does not fit the LDS");
     } else if (o.steps_per_launch == 3) {
         // three forward-type steps and two adjoint steps per launch
@@ -770,7 +811,7 @@ static fwi_status create_impl(fwi_plan* p, fwi_dtype dtype, const fwi_grid* grid
             int S = p->S;
             for (auto& it : p->items)
                 if (S >= 2 && it.K < 4 && it.K < p->media[it.medium].g.nt) S = 1;
-            const int Sa = std::min(S, 2);
+            const int Sa = adjoint_steps(p->order, S);
             double exec = 0, launches = 0;
             for (auto& it : p->items) {
                 const MediumPlan& m = p->media[it.medium];
@@ -830,7 +871,7 @@ static fwi_status create_impl(fwi_plan* p, fwi_dtype dtype, const fwi_grid* grid
     if (p->S >= 2)
         for (auto& it : p->items)
             if (it.K < 4 && it.K < p->media[it.medium].g.nt) p->S = 1;
-    p->Sa = std::min(p->S, 2);
+    p->Sa = adjoint_steps(p->order, p->S);
     p->nlam = p->Sa == 2 ? 4 : 2;
     for (auto& it : p->items) {
         const int T = p->media[it.medium].g.nt;
@@ -1186,7 +1227,10 @@ void fill_items(fwi_plan* p, const fwi_io* io, unsigned char* ws, bool adj_from_
         d.entries_x = reinterpret_cast<const Entry*>(tabs + ip.entry_x_off);
         d.S = p->S;
         d.Sa = p->Sa;
-        d.nlam = p->nlam;
+        d.nlam = p->nlam;                         // 2 or 4: levels are taken modulo it by a mask
+        d.sc = make_sched(m.g.nt, ip.K, ip.J, p->S, p->Sa);
+        d.dtx = make_div((uint32_t)ip.tiles_x);
+        d.dnx = make_div((uint32_t)m.g.nx);
         // the adjoint of the last segment reads levels (J-1)K + 1 .. T of the first pass
         d.keep_from = p->opt.forward_only ? INT_MAX : (ip.J - 1) * ip.K + 1;
         d.eatt = p->att ? reinterpret_cast<const T*>(ws + m.eatt_off) : nullptr;

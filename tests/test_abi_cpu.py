@@ -108,7 +108,7 @@ def _grid(**kw):
     ({}, dict(order=3), 1),
     (dict(c_max=3100.0), dict(order=4), 2),                 # c dt/h = 0.62 > 0.606 (order 4 only)
     ({}, dict(order=4, persistent=True), 1),
-    ({}, dict(order=4, steps_per_launch=2), 1),
+    ({}, dict(order=4, dtype="f64", rows=4), 1),            # FP64 fourth-order faces of 64 x 16 tiles > LDS
     ({}, dict(order=4, rows=8), 1),
     (dict(nx=20000, nz=20000), {}, 1),                      # a field plane of 4 transmits >= 4 GiB
     (dict(nx=12000, nz=12000), dict(dtype="f64"), 1),       # FP64: 144e6 cells x 4 x 8 B >= 4 GiB

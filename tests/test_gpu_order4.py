@@ -56,6 +56,31 @@ def test_fourth_order_parity(dtype, mode, group, rows, ckpt):
     _check(res[0], ref, dtype)
 
 
+@pytest.mark.parametrize("rows", [1, 2, 4])
+def test_fourth_order_two_step_bitwise(rows):
+    """Two forward steps per launch (the first on the tile grown by three,
+    out-of-grid cells kept zero) equal one step per launch bitwise, store-all
+    and with an odd checkpoint interval (recompute runs pair other levels and
+    end in one-step launches); ragged 150 x 77, sources and receivers on and
+    next to the border."""
+    m = _medium(7, 150, 77, 301, n_tx=3, n_rcv=9, npml=4, courant=0.45, dup_receiver=True)
+    g = m.geom
+    g.rcv[0, 1] = 0
+    g.rcv[1, 2] = g.nx * g.nz - 1
+    g.src[1] = g.nx - 1
+    g.src[2] = 2 * g.nx + g.nx - 2
+    obs = _observed(m, 3)
+    print(f"[o4] two-step bitwise, rows {rows}", flush=True)
+    one, p1 = gpu_run([m], [obs], dtype="f32", order=4, rows=rows, steps_per_launch=1, ckpt=10**6)
+    assert p1.info["steps_per_launch"] == 1
+    for K in (10**6, 7):
+        two, p2 = gpu_run([m], [obs], dtype="f32", order=4, rows=rows, ckpt=K, steps_per_launch=2)
+        assert p2.info["steps_per_launch"] == 2
+        for k in ("traces", "grad_c", "grad_rho", "misfit"):
+            assert np.array_equal(two[0][k], one[0][k]), (K, k)
+    _check(one[0], oracle_grad(m, obs), "f32")
+
+
 def test_fourth_order_differs_from_second():
     """The plan's order reaches the kernels: order-2 GPU traces differ from
     the order-4 oracle by far more than rounding."""

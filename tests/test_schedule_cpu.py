@@ -25,13 +25,16 @@ def dump():
     r = subprocess.run(cmd, capture_output=True, text=True)
     assert r.returncode == 0, r.stderr[-2000:]
 
+    r = subprocess.run([exe, "div"], capture_output=True, text=True)
+    assert r.returncode == 0, "multiply-shift division differs from n / d: " + r.stdout
+
     def run(T, K, S, Sa):
         out = subprocess.run([exe, str(T), str(K), str(S), str(Sa)], capture_output=True, text=True, check=True).stdout
         return [tuple(int(v) for v in l.split()) for l in out.splitlines()]
     return run
 
 
-CASES = [(T, K, S, Sa) for S, Sa in ((1, 1), (2, 2), (3, 2)) for T, K in
+CASES = [(T, K, S, Sa) for S, Sa in ((1, 1), (2, 1), (2, 2), (3, 2)) for T, K in
          [(1, 1), (2, 2), (3, 3), (5, 2), (7, 3), (10, 4), (11, 4), (64, 8), (65, 8), (100, 14), (101, 14),
           (120, 120), (37, 36), (4000, 90), (3407, 82), (100, 12), (4000, 84)]]
 
@@ -146,3 +149,31 @@ class _FakeBuf:
 
     def element_size(self):
         return 1
+
+
+@pytest.mark.parametrize("dtype,rows", [("f32", 1), ("f32", 2), ("f64", 1)])
+def test_fourth_order_launch_list(dtype, rows):
+    """Fourth-order plans (two forward steps per launch, one adjoint step),
+    listed on the host: two-step forward launches with one-step tails, every
+    step kernel's dynamic LDS within gfx950's per-workgroup limit, launch
+    counts as the plan reports them; an odd checkpoint interval gives
+    recompute runs ending in one-step launches."""
+    import numpy as np
+    import paper_2603_04070_amd as F
+    g = F.GridSpec(nx=300, nz=171, nt=301, h=1e-4, dt=1.5e-8, src=np.arange(5, dtype=np.int32) * 7 + 40 * 300,
+                   rcv=np.tile(np.arange(9, dtype=np.int32) * 11 + 50 * 300 + 3, (5, 1)), npml=12)
+    for K in (10 ** 6, 9):
+        plan = F.Plan([g], dtype=dtype, order=4, rows=rows, ckpt=K, mem_budget=4e9, host_only=True,
+                      steps_per_launch=2)
+        assert plan.info["steps_per_launch"] == 2
+        L = [l for l in plan.launches("execute") if l["step"] >= 0]
+        assert len(L) == plan.info["launches"]
+        kinds = {l["kernel"] for l in L}
+        assert kinds <= {"fwd4x2", "fwd4", "adj4"} and {"fwd4x2", "adj4"} <= kinds, kinds
+        assert "fwd4" in kinds                      # nt odd: the forward pass ends in one step
+        for l in L:
+            assert l["block"] == 256 and 0 < l["lds_bytes"] <= GFX950_LDS_PER_WORKGROUP, l
+        one = F.Plan([g], dtype=dtype, order=4, rows=rows, ckpt=K, mem_budget=4e9, host_only=True,
+                     steps_per_launch=1)
+        assert one.info["steps_per_launch"] == 1
+        assert {l["kernel"] for l in one.launches("execute") if l["step"] >= 0} == {"fwd4", "adj4"}
