@@ -938,7 +938,8 @@ struct Lds2 {
     static constexpr int P0 = (N0 + kBlock - 1) / kBlock;               // per-thread shares
     static constexpr int P1 = (N1 + kBlock - 1) / kBlock;
     static constexpr int ND = W0 + H0;                                  // damping: columns, then rows
-    static_assert(ND <= kBlock, "one damping value per thread");
+    static constexpr int NR1 = 2 * W1 + 2 * TZ;                         // ring of the tile grown by 1
+    static_assert(ND <= kBlock && NR1 <= kBlock, "one damping value and ring cell per thread");
     // F0[N0] fields, Q0[N0] and B0[N0] coefficients (separate arrays: unit-stride
     // neighbour reads), then (adjoint only) two tile + 1 field planes without
     // their first and last cells, the top-left and bottom-right corners that
@@ -1403,9 +1404,15 @@ __device__ void tile_adjoint2(const Item<T, Acc>& it, const Step& st, int tile_x
     // one burst: lam^t and (q, bt) on the tile grown by 2; lam^{t+1}, u^{t-1},
     // u^{t-2} on the tile grown by 1; the damping profile; this thread's
     // imaging accumulators
-    Vec<T, G> f0[L::P0], pv[L::P1], ua[L::P1], ub[L::P1];
+    Vec<T, G> f0[L::P0], ua[L::P1], ub[L::P1], pvt[R], pvr;
     T q0[L::P0], b0[L::P0];
     Acc sK[R], sB[R];
+    // this lane's cell of the ring between the tile and the tile grown by
+    // one (grown-tile coordinates), for the lam^{t-1} it computes there
+    int rex = 0, rez = 0;
+    ring_cell<L::W1, L::TZ>(tid, rex, rez);
+    const int rx1 = x0 - 1 + rex, rz1 = z0 - 1 + rez;
+    const bool rin = tid < L::NR1 && rx1 >= 0 && rx1 < nx && rz1 >= 0 && rz1 < nz;
 #pragma unroll
     for (int i = 0; i < L::P0; ++i) {
         const int c = tid + i * kBlock;
@@ -1425,7 +1432,6 @@ __device__ void tile_adjoint2(const Item<T, Acc>& it, const Step& st, int tile_x
         cell_of<T, G, R, true>(c, 1, x0, z0, ix1, iz1);
         const bool in = c < L::N1 && ix1 >= 0 && ix1 < nx && iz1 >= 0 && iz1 < nz;
         const uint32_t x = in ? (uint32_t)(iz1 * nx + ix1) : 0u;
-        pv[i] = vkeep<T, G>(in, vload32<T, G>(p1, x));
         ua[i] = vkeep<T, G>(in, vload32<T, G>(um1, x));
         ub[i] = vkeep<T, G>(in, vload32<T, G>(um2, x));
     }
@@ -1435,7 +1441,9 @@ __device__ void tile_adjoint2(const Item<T, Acc>& it, const Step& st, int tile_x
         const uint32_t x = ix < nx && iz < nz ? (uint32_t)(iz * nx + ix) : 0u;
         sK[k] = ldg32(accK, x);
         sB[k] = ldg32(accB, x);
+        pvt[k] = vload32<T, G>(p1, x);
     }
+    pvr = vload32<T, G>(p1, rin ? (uint32_t)(rz1 * nx + rx1) : 0u);
     const T dmp = damping_of<T, L::W0, L::ND>(exd_p, ezd_p, nx, nz, tid, x0, z0);
 #pragma unroll
     for (int i = 0; i < L::P0; ++i) {
@@ -1456,31 +1464,23 @@ __device__ void tile_adjoint2(const Item<T, Acc>& it, const Step& st, int tile_x
     }
     if (tid < L::ND) D[tid] = dmp;
     __syncthreads();
-    // lam^{t-1} on the tile grown by one cell, into registers until X is free
-    Vec<T, G> m1[L::P1];
+    // lam^{t-1} on the tile grown by one cell, into registers until X is
+    // free: at this lane's ring cell, then at its R tile cells together with
+    // the imaging of (lam^t, u^{t-1}) there (summed over the transmits), which
+    // shares the cell's face buoyancies and differences of lam^t
+    Vec<T, G> m1r = vzero<T, G>(), m1t[R];
+    if (rin) {
+        const int k = (rez + 1) * L::W0 + rex + 1;
+        T fw, fe, fn, fs, a, b;
+        faces<T>(rx1 > 0, rx1 < nx - 1, rz1 > 0, rz1 < nz - 1, B0[k], B0[k - 1], B0[k + 1], B0[k - L::W0],
+                 B0[k + L::W0], fw, fe, fn, fs);
+        damp_coeffs<T>(D[rex + 1] + D[L::W0 + rez + 1], a, b);
+        const T qc = Q0[k];
+        const Vec<T, G> l0 = L0[k], lw = L0[k - 1], le = L0[k + 1], ln = L0[k - L::W0], ls = L0[k + L::W0];
 #pragma unroll
-    for (int i = 0; i < L::P1; ++i) {
-        const int c = tid + i * kBlock;
-        m1[i] = vzero<T, G>();
-        if (c < L::N1) {
-            const int ex = c % L::W1, ez = c / L::W1;
-            const int ix1 = x0 - 1 + ex, iz1 = z0 - 1 + ez;
-            if (ix1 >= 0 && ix1 < nx && iz1 >= 0 && iz1 < nz) {
-                const int k = (ez + 1) * L::W0 + ex + 1;
-                T fw, fe, fn, fs, a, b;
-                faces<T>(ix1 > 0, ix1 < nx - 1, iz1 > 0, iz1 < nz - 1, B0[k], B0[k - 1],
-                         B0[k + 1], B0[k - L::W0], B0[k + L::W0], fw, fe, fn, fs);
-                damp_coeffs<T>(D[ex + 1] + D[L::W0 + ez + 1], a, b);
-                const T qc = Q0[k];
-                const Vec<T, G> l0 = L0[k], lw = L0[k - 1], le = L0[k + 1], ln = L0[k - L::W0], ls = L0[k + L::W0];
-#pragma unroll
-                for (int g = 0; g < G; ++g)
-                    m1[i].v[g] = adjw_cell<T>(a, b, qc, fw, fe, fn, fs, l0.v[g], lw.v[g], le.v[g], ln.v[g],
-                                              ls.v[g], pv[i].v[g]);
-            }
-        }
+        for (int g = 0; g < G; ++g)
+            m1r.v[g] = adjw_cell<T>(a, b, qc, fw, fe, fn, fs, l0.v[g], lw.v[g], le.v[g], ln.v[g], ls.v[g], pvr.v[g]);
     }
-    // on the tile: the imaging of (lam^t, u^{t-1}), summed over the transmits
     const bool hw = ix > 0, he = ix < nx - 1;
     const T hf = T(0.5);
     const T cw = hw ? hf : T(1), ce = he ? hf : T(1);
@@ -1488,20 +1488,25 @@ __device__ void tile_adjoint2(const Item<T, Acc>& it, const Step& st, int tile_x
 #pragma unroll
     for (int k = 0; k < R; ++k) {
         const int ez = (int)threadIdx.y * R + k, iz = z0 + ez;
+        m1t[k] = vzero<T, G>();
         ska[k] = Acc(0);
         sba[k] = Acc(0);
         if (ix < nx && iz < nz) {
             const int k1 = (ez + 1) * L::W1 + threadIdx.x + 1;
             const int k0 = (ez + 2) * L::W0 + threadIdx.x + 2;
             const bool hn = iz > 0, hs = iz < nz - 1;
-            T fw, fe, fn, fs;
+            T fw, fe, fn, fs, a, b;
             faces<T>(hw, he, hn, hs, B0[k0], B0[k0 - 1], B0[k0 + 1], B0[k0 - L::W0], B0[k0 + L::W0], fw, fe, fn, fs);
+            damp_coeffs<T>(D[threadIdx.x + 2] + D[L::W0 + ez + 2], a, b);
             const T cn = hn ? hf : T(1), cs = hs ? hf : T(1);
+            const T qc = Q0[k0];
             const Vec<T, G> l0 = L0[k0], lw = L0[k0 - 1], le = L0[k0 + 1], ln = L0[k0 - L::W0],
                             ls = L0[k0 + L::W0];
             const Vec<T, G> a0 = X[k1], aw = X[k1 - 1], ae = X[k1 + 1], an = X[k1 - L::W1], as = X[k1 + L::W1];
 #pragma unroll
             for (int g = 0; g < G; ++g) {
+                m1t[k].v[g] = adjw_cell<T>(a, b, qc, fw, fe, fn, fs, l0.v[g], lw.v[g], le.v[g], ln.v[g], ls.v[g],
+                                           pvt[k].v[g]);
                 T k1a, b1a;
                 image_cell<T>(fw, fe, fn, fs, cw, ce, cn, cs, l0.v[g], l0.v[g], lw.v[g], le.v[g], ln.v[g], ls.v[g],
                               a0.v[g], aw.v[g], ae.v[g], an.v[g], as.v[g], k1a, b1a);
@@ -1511,11 +1516,14 @@ __device__ void tile_adjoint2(const Item<T, Acc>& it, const Step& st, int tile_x
         }
     }
     __syncthreads();
-#pragma unroll
-    for (int i = 0; i < L::P1; ++i) {
-        const int c = tid + i * kBlock;
-        if (c > 0 && c < L::N1 - 1) X[c] = m1[i];
+    // the two corner cells of the grown tile, which no tile cell reads, are
+    // not stored (X leaves them out)
+    if (tid < L::NR1) {
+        const int c = rez * L::W1 + rex;
+        if (c > 0 && c < L::N1 - 1) X[c] = m1r;
     }
+#pragma unroll
+    for (int k = 0; k < R; ++k) X[((int)threadIdx.y * R + k + 1) * L::W1 + threadIdx.x + 1] = m1t[k];
     __syncthreads();
     // adjoint source of lam^{t-1} (sample t-2, times q) at the receivers of
     // the grown tile (the two corner cells that X does not hold are read by
