@@ -164,15 +164,18 @@ def run_unfold(args):
     dev = torch.device("cuda:0")
     media = [W.c2_medium(5000 + i, n_tx=32) for i in range(16)]
     partners = [W.partner_medium(m, 6000 + i) for i, m in enumerate(media)]
+    progress("unfold workload built: 16 media 512^2, 32 transmits")
     if args.nt > 0:
         for m in media + partners:
             m.geom.nt = args.nt
             m.wavelet = m.wavelet[:, :args.nt]
     c_max = 1700.0
     d_obs = observed(partners, "f32", args, c_max, dev)
+    progress("observed traces computed")
     grids = [F.GridSpec.of(m.geom, c_max) for m in media]
     torch.manual_seed(0)
     model = DUFWI(grids, K=args.unfold_k, arch="small", hidden=32, physics_backprop=args.unfold_backprop).to(dev)
+    progress("unfolded network built")
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float32)).to(dev)
     c0 = torch.full((16, 512, 512), 1540.0, device=dev)
     rho = torch.stack([t(m.rho) for m in media])
@@ -187,6 +190,7 @@ def run_unfold(args):
         cK = model(c_in, rho, wav, d_obs)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
+        progress(f"unfold iteration {it}: forward {t1 - t0:.1f} s")
         loss = ((cK - target) ** 2).mean()
         loss.backward()
         torch.cuda.synchronize()
