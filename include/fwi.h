@@ -125,9 +125,11 @@ typedef struct fwi_options {
     int32_t order;           /* spatial order of the operator: 0 or 2 = the 5-point flux form of */
                              /*    eq. 1-2; 4 = staggered fourth-order differences (rows 1, 2 or */
                              /*    4, not persistent; stability bound with 98/9 in place of 8)   */
-    int32_t hvp;             /* 1: the plan serves fwi_plan_hvp only (one step per launch, order */
-                             /*    2, not persistent, no graph, not forward_only; its workspace  */
-                             /*    holds value and derivative of every field)                    */
+    int32_t hvp;             /* 1: the plan serves fwi_plan_hvp only (order 2, not persistent,  */
+                             /*    no graph, not forward_only; groups of 2 by default, with the  */
+                             /*    default multi-step launches; groups of 4 run one step per     */
+                             /*    launch; its workspace holds value and derivative of every     */
+                             /*    field)                                                        */
     int32_t host_only;       /* 1: plan on the host only, with no HIP call (mem_budget > 0       */
                              /*    required): sizes, info and fwi_plan_launches work, the calls  */
                              /*    return FWI_ERR_INVALID                                        */

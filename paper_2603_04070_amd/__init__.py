@@ -92,7 +92,8 @@ class Plan:
     ``order``: 2 (the 5-point flux form) or 4 (staggered fourth-order
     differences: one forward-type step per launch, or two with
     ``steps_per_launch=2``; one adjoint step).  ``hvp``: the plan serves
-    ``hessian_vector`` (fwi_plan_hvp) only.  ``host_only``: plan on the host
+    ``hessian_vector`` (fwi_plan_hvp) only (groups of 2 and multi-step
+    launches by default; groups of 4 run one step per launch).  ``host_only``: plan on the host
     without any HIP call (needs ``mem_budget``): sizes, ``info`` and
     ``launches`` only.  ``single_wave``: keep every item resident at once
     (needed by ``forward`` / ``adjoint``); otherwise an automatic ``ckpt``

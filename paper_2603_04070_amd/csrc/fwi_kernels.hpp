@@ -296,23 +296,34 @@ __device__ __forceinline__ void vstore(T* p, int64_t cell, const Vec<T, G>& v)
 // access takes the scalar-base form (64-bit base in SGPRs, 32-bit offset per
 // lane) instead of 64-bit address arithmetic in every lane.  Plans keep every
 // plane and coefficient array below 4 GiB, so the offsets cannot wrap.
+// (Dual fields take the pairwise accesses above.)
 template <typename T>
 __device__ __forceinline__ T ldg32(const T* p, uint32_t i)
 {
+    if constexpr (DualOf<T>::is) {
+        return ldg(p, (int64_t)i);
+    } else {
     using B = const char __attribute__((address_space(1)))*;
     return *(const T __attribute__((address_space(1)))*)((B)p + i * (uint32_t)sizeof(T));
+    }
 }
 
 template <typename T>
 __device__ __forceinline__ void stg32(T* p, uint32_t i, T v)
 {
+    if constexpr (DualOf<T>::is) {
+        stg(p, (int64_t)i, v);
+    } else {
     using B = char __attribute__((address_space(1)))*;
     *(T __attribute__((address_space(1)))*)((B)p + i * (uint32_t)sizeof(T)) = v;
+    }
 }
 
 template <typename T, int G>
 __device__ __forceinline__ Vec<T, G> vload32(const T* p, uint32_t cell)
 {
+    if constexpr (DualOf<T>::is) return vload<T, G>(p, (int64_t)cell);
+    else {
     using N = typename Native<T, G>::type;
     using B = const char __attribute__((address_space(1)))*;
     const N n = *(const N __attribute__((address_space(1)))*)((B)p + cell * (uint32_t)(sizeof(T) * G));
@@ -324,11 +335,16 @@ __device__ __forceinline__ Vec<T, G> vload32(const T* p, uint32_t cell)
         for (int g = 0; g < G; ++g) r.v[g] = n[g];
     }
     return r;
+    }
 }
 
 template <typename T, int G>
 __device__ __forceinline__ void vstore32(T* p, uint32_t cell, const Vec<T, G>& v)
 {
+    if constexpr (DualOf<T>::is) {
+        vstore<T, G>(p, (int64_t)cell, v);
+        return;
+    } else {
     using N = typename Native<T, G>::type;
     using B = char __attribute__((address_space(1)))*;
     N n;
@@ -339,6 +355,7 @@ __device__ __forceinline__ void vstore32(T* p, uint32_t cell, const Vec<T, G>& v
         for (int g = 0; g < G; ++g) n[g] = v.v[g];
     }
     *(N __attribute__((address_space(1)))*)((B)p + cell * (uint32_t)(sizeof(T) * G)) = n;
+    }
 }
 
 template <typename T, int G>

@@ -373,6 +373,7 @@ size_t step_lds(const fwi_plan* p, int kind)
         if (p->G == 2) return lds_of<T, 2>(kind, p->rows, p->order);
         return lds_of<T, 4>(kind, p->rows, p->order);
     };
+    if (p->hvp) return p->dtype == FWI_F64 ? byG(Dual<double>()) : byG(Dual<float>());
     return p->dtype == FWI_F64 ? byG(double()) : byG(float());
 }
 
@@ -401,6 +402,25 @@ hipError_t allow_lds_plan(const fwi_plan* p)
         if (p->G == 2) return allow_lds_r<T, A, 2>(p->rows, p->order);
         return allow_lds_r<T, A, 4>(p->rows, p->order);
     };
+    if (p->hvp) {
+        // dual instantiations run multi-step launches with groups of 1 or 2 only
+        auto pick_h = [&](auto t, auto a) -> hipError_t {
+            using T = decltype(t);
+            using A = decltype(a);
+            auto byR = [&](auto g) -> hipError_t {
+                constexpr int GG = decltype(g)::value;
+                if (p->rows == 1) return allow_lds<T, A, GG, 1>();
+                if (p->rows == 2) return allow_lds<T, A, GG, 2>();
+                return allow_lds<T, A, GG, 4>();
+            };
+            if (p->G == 1) return byR(std::integral_constant<int, 1>());
+            if (p->G == 2) return byR(std::integral_constant<int, 2>());
+            return hipSuccess;
+        };
+        if (p->dtype == FWI_F64) return pick_h(Dual<double>(), Dual<double>());
+        if (p->acc_double) return pick_h(Dual<float>(), Dual<double>());
+        return pick_h(Dual<float>(), Dual<float>());
+    }
     if (p->dtype == FWI_F64) return pick(double(), double());
     if (p->acc_double) return pick(float(), double());
     return pick(float(), float());
@@ -578,9 +598,9 @@ static fwi_status create_impl(fwi_plan* p, fwi_dtype dtype, const fwi_grid* grid
     if (o.attenuation && (o.order == 4 || o.persistent || o.hvp || o.steps_per_launch > 1))
         return fail(p, FWI_ERR_INVALID, "attenuation runs the second-order operator one step per launch, "
                                         "not persistent, not hvp");
-    if (o.hvp && (o.order == 4 || o.persistent || o.use_graph || o.forward_only || o.steps_per_launch > 1))
-        return fail(p, FWI_ERR_INVALID, "hvp plans run the second-order operator one step per launch, "
-                                        "not persistent, without graph, not forward-only");
+    if (o.hvp && (o.order == 4 || o.persistent || o.use_graph || o.forward_only || (o.group == 4 && o.steps_per_launch > 1)))
+        return fail(p, FWI_ERR_INVALID, "hvp plans run the second-order operator, not persistent, without graph, "
+                                        "not forward-only, several steps per launch with groups of 1 or 2 only");
     if (o.order == 4) {
         if (o.persistent) return fail(p, FWI_ERR_INVALID, "the fourth-order operator has no persistent form");
         if (o.steps_per_launch >= 3)
@@ -596,7 +616,9 @@ static fwi_status create_impl(fwi_plan* p, fwi_dtype dtype, const fwi_grid* grid
 
     p->dtype = dtype;
     p->opt = o;
-    p->G = o.group ? o.group : (o.mode == FWI_PLAIN ? 1 : 4);
+    // hvp plans: groups of 2 by default, so that the dual fields of the
+    // multi-step kernels take the LDS of four FP32 transmits
+    p->G = o.group ? o.group : (o.mode == FWI_PLAIN ? 1 : o.hvp ? 2 : 4);
     // default: three forward-type and two adjoint steps per launch on 64 x 8
     // tiles (one step on 64 x 16 for the plain form); with an explicit rows
     // value that multi-step tiles do not support, one step
@@ -605,7 +627,7 @@ static fwi_status create_impl(fwi_plan* p, fwi_dtype dtype, const fwi_grid* grid
         // LDS of the two-step adjoint: tile + 2 (fields, q, bt) and two tile + 1
         // field planes less their two corner cells
         const size_t n0 = (size_t)(kTileX + 4) * (kWavesZ * rows + 4), n1 = (size_t)(kTileX + 2) * (kWavesZ * rows + 2);
-        const size_t ts = dtype == FWI_F64 ? 8 : 4;
+        const size_t ts = (dtype == FWI_F64 ? 8 : 4) * (o.hvp ? 2 : 1);
         return (n0 * (p->G + 2) + 2 * (n1 - 2) * p->G) * ts <= kLdsBytes;
     };
     p->order = o.order == 4 ? 4 : 2;
@@ -627,7 +649,7 @@ static fwi_status create_impl(fwi_plan* p, fwi_dtype dtype, const fwi_grid* grid
         p->rows = o.rows ? o.rows : 2;
         if (!two_step_ok(p->rows))
             return fail(p, FWI_ERR_INVALID, "two steps per launch need rows of 1, 2 or 4 whose tile fits the LDS");
-    } else if (o.steps_per_launch == 1 || o.mode == FWI_PLAIN || o.hvp || o.attenuation) {
+    } else if (o.steps_per_launch == 1 || o.mode == FWI_PLAIN || (o.hvp && p->G == 4) || o.attenuation) {
         p->S = 1;
         p->rows = o.rows ? o.rows : 4;
     } else {
@@ -1412,8 +1434,16 @@ void step_hvp_t(int G, int kind, dim3 grid, hipStream_t st, const void* items, c
     auto go = [&](auto g) {
         constexpr int GG = decltype(g)::value;
         const auto* it = reinterpret_cast<const Item<T, Acc>*>(items);
-        if (kind == 0) hipLaunchKernelGGL((fwd1_kernel<T, GG, Acc>), grid, blk, 0, st, it, blocks, s, (int)kRunAll, rows);
-        else hipLaunchKernelGGL((adj1_kernel<T, GG, Acc>), grid, blk, 0, st, it, blocks, s, (int)kRunAll, rows);
+        if (kind == 0) {
+            hipLaunchKernelGGL((fwd1_kernel<T, GG, Acc>), grid, blk, 0, st, it, blocks, s, (int)kRunAll, rows);
+        } else if (kind == 2) {
+            hipLaunchKernelGGL((adj1_kernel<T, GG, Acc>), grid, blk, 0, st, it, blocks, s, (int)kRunAll, rows);
+        } else if constexpr (GG <= 2) {
+            // two- and three-step launches (plans with groups of 4 run one step)
+            if (rows == 1) launch2<T, Acc, GG, 1>(kind, grid, st, it, blocks, s, (int)kRunAll);
+            else if (rows == 2) launch2<T, Acc, GG, 2>(kind, grid, st, it, blocks, s, (int)kRunAll);
+            else launch2<T, Acc, GG, 4>(kind, grid, st, it, blocks, s, (int)kRunAll);
+        }
     };
     if (G == 1) go(std::integral_constant<int, 1>());
     else if (G == 2) go(std::integral_constant<int, 2>());
@@ -1422,7 +1452,7 @@ void step_hvp_t(int G, int kind, dim3 grid, hipStream_t st, const void* items, c
 
 void step_hvp(fwi_plan* p, int kind, dim3 grid, hipStream_t st, const int2* blocks, int s)
 {
-    if (recording()) { record(kind == 0 ? FWI_K_FWD1 : FWI_K_ADJ1, grid, dim3(kTileX, kWavesZ), 0); return; }
+    if (recording()) { record(kind, grid, dim3(kTileX, kWavesZ), step_lds(p, kind)); return; }
     if (p->dtype == FWI_F64) step_hvp_t<Dual<double>, Dual<double>>(p->G, kind, grid, st, p->d_items, blocks, s, p->rows);
     else if (p->acc_double) step_hvp_t<Dual<float>, Dual<double>>(p->G, kind, grid, st, p->d_items, blocks, s, p->rows);
     else step_hvp_t<Dual<float>, Dual<float>>(p->G, kind, grid, st, p->d_items, blocks, s, p->rows);
@@ -1483,8 +1513,8 @@ void enqueue_hvp(fwi_plan* p, hipStream_t st, unsigned char* ws)
             const unsigned kinds = wave_kinds(p, w, s, kRunAll, &n_active);
             const dim3 grid((unsigned)w.prefix[n_active]);
             g_rec.step = s;
-            if (kinds & 1u) step_hvp(p, 0, grid, st, p->d_blocks + w.blk0, s);
-            if (kinds & 4u) step_hvp(p, 2, grid, st, p->d_blocks + w.blk0, s);
+            for (int k = 0; k < 5; ++k)
+                if (kinds & (1u << k)) step_hvp(p, k, grid, st, p->d_blocks + w.blk0, s);
         }
         g_rec.step = -1;
     }

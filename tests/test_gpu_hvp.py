@@ -113,3 +113,22 @@ def test_hvp_checkpoint_bitwise_and_media_in_waves():
             assert np.array_equal(x[k], y[k]), k
             assert np.array_equal(x[k], z[k]), k
     _check(r_ck[1], _oracle(b[0], b[1], b[2], None), 1e-5, 1e-4, 1e-4)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_hvp_multistep_bitwise(dtype):
+    """Hessian-vector plans with groups of 2 fuse three forward-type and two
+    adjoint steps per launch on the dual fields; the results equal one step
+    per launch bitwise (store-all and an interval that is not a multiple of
+    the fused steps), and match the oracle."""
+    m, obs, dc, drho = _case(16, 150, 110, 251, 4, npml=4)
+    print(f"[hvp] {dtype} multi-step against one step per launch, groups of 2", flush=True)
+    ref, p1 = _gpu([m], [obs], [(dc, drho)], dtype, ckpt=10**6, group=2, steps_per_launch=1)
+    assert p1.info["steps_per_launch"] == 1
+    for K, spl in ((10**6, 0), (10**6, 2), (13, 0)):
+        res, plan = _gpu([m], [obs], [(dc, drho)], dtype, ckpt=K, group=2, steps_per_launch=spl)
+        assert plan.info["steps_per_launch"] == (spl or 3)
+        for k in ("traces", "dtraces", "grad_c", "grad_rho", "hv_c", "hv_rho", "misfit"):
+            assert np.array_equal(res[0][k], ref[0][k]), (K, spl, k)
+    tol = (1e-10, 1e-10, 1e-8) if dtype == "f64" else (1e-5, 1e-4, 1e-4)
+    _check(ref[0], _oracle(m, obs, dc, drho), *tol)

@@ -177,3 +177,28 @@ def test_fourth_order_launch_list(dtype, rows):
                      steps_per_launch=1)
         assert one.info["steps_per_launch"] == 1
         assert {l["kernel"] for l in one.launches("execute") if l["step"] >= 0} == {"fwd4", "adj4"}
+
+
+def test_hvp_plan_fuses_steps_with_groups_of_two():
+    """Hessian-vector plans default to groups of 2 with three forward-type
+    and two adjoint steps per launch on the dual fields (dynamic LDS within
+    the limit); groups of 4 run one step per launch and refuse more."""
+    import numpy as np
+    import paper_2603_04070_amd as F
+    g = F.GridSpec(nx=300, nz=171, nt=301, h=1e-4, dt=2e-8, src=np.arange(5, dtype=np.int32) * 7 + 40 * 300,
+                   rcv=np.tile(np.arange(9, dtype=np.int32) * 11 + 50 * 300 + 3, (5, 1)), npml=12)
+    for dtype in ("f32", "f64"):
+        plan = F.Plan([g], dtype=dtype, hvp=True, mem_budget=8e9, host_only=True)
+        assert plan.info["group"] == 2 and plan.info["steps_per_launch"] == 3
+        L = [l for l in plan.launches("hvp") if l["step"] >= 0]
+        assert len(L) == plan.info["launches"]
+        kinds = {l["kernel"] for l in L}
+        assert {"fwd3", "adj2"} <= kinds <= {"fwd1", "fwd2", "fwd3", "adj1", "adj2"}, kinds
+        for l in L:
+            assert l["block"] == 256 and 0 <= l["lds_bytes"] <= GFX950_LDS_PER_WORKGROUP, l
+            if l["kernel"] in ("fwd2", "fwd3", "adj2"):
+                assert l["lds_bytes"] > 0, l
+    one = F.Plan([g], dtype="f32", hvp=True, group=4, mem_budget=8e9, host_only=True)
+    assert one.info["steps_per_launch"] == 1
+    with pytest.raises(F.FwiError):
+        F.Plan([g], dtype="f32", hvp=True, group=4, steps_per_launch=3, mem_budget=8e9, host_only=True)
