@@ -524,6 +524,20 @@ __device__ __forceinline__ T fwd_cell(T nb, T c2, T q, T fw, T fe, T fn, T fs, T
     return fma(q, L, fma(nb, v0, c2 * u0));
 }
 
+// The same update where no damping acts (-beta = 1, c2 = 0): v0 + q L.  It
+// equals fwd_cell's value there (the two vanishing terms add a signed zero
+// at most).
+template <typename T>
+__device__ __forceinline__ T fwd_cell_free(T q, T fw, T fe, T fn, T fs, T u0, T uw, T ue, T un, T us, T v0)
+{
+#pragma clang fp contract(off)
+    T L = fw * (uw - u0);
+    L = fma(fe, ue - u0, L);
+    L = fma(fn, un - u0, L);
+    L = fma(fs, us - u0, L);
+    return fma(q, L, v0);
+}
+
 // One cell of the adjoint update: a l0 + b lp + sum_f b_f (w_f - w0), w = q l.
 template <typename T>
 __device__ __forceinline__ T adj_cell(T a, T b, T fw, T fe, T fn, T fs, T w0, T ww, T we, T wn, T ws, T l0, T lp)
@@ -1286,7 +1300,14 @@ __device__ void tile_forward3(const Item<T, Acc>& it, const Step& st, int tile_x
         }
     }
     if (tid < L::ND) D[tid] = dmp;
-    __syncthreads();
+    // no absorbing layer within the tile grown by three: -beta = 1 and c2 = 0
+    // at every cell this launch updates (a wave-uniform branch below; dual
+    // fields keep the general update)
+    bool damp = true;
+    if constexpr (DualOf<T>::is)
+        __syncthreads();
+    else
+        damp = __syncthreads_or(tid < L::ND && dmp != T(0)) != 0;
 
     // one step at cell (x, z) of the grid (tile-relative) from the level in
     // U: v of the next level into vv (v of this level given there), u of the
@@ -1295,19 +1316,42 @@ __device__ void tile_forward3(const Item<T, Acc>& it, const Step& st, int tile_x
         const int gx = x0 + x, gz = z0 + z;
         const int k = (z + 3) * W + x + 3;
         const int cell = gz * nx + gx;
-        T fw, fe, fn, fs, nb, c2;
+        T fw, fe, fn, fs;
         faces<T>(gx > 0, gx < nx - 1, gz > 0, gz < nz - 1, B[k], B[k - 1], B[k + 1], B[k - W], B[k + W],
                  fw, fe, fn, fs);
-        damp_inc<T>(D[x + 3] + D[W + z + 3], nb, c2);
-        const T qc = Q[k];
-        const Vec<T, G> u0 = U[k], uw = U[k - 1], ue = U[k + 1], un = U[k - W], us = U[k + W];
         Vec<T, G> r;
+        if constexpr (DualOf<T>::is) {
+            T nb, c2;
+            damp_inc<T>(D[x + 3] + D[W + z + 3], nb, c2);
+            const T qc = Q[k];
+            const Vec<T, G> u0 = U[k], uw = U[k - 1], ue = U[k + 1], un = U[k - W], us = U[k + W];
 #pragma unroll
-        for (int g = 0; g < G; ++g)
-            vv.v[g] = fwd_cell<T>(nb, c2, qc, fw, fe, fn, fs, u0.v[g], uw.v[g], ue.v[g], un.v[g], us.v[g], vv.v[g]);
-        if (near) add_src<T, G>(vv, cell, sc);
+            for (int g = 0; g < G; ++g)
+                vv.v[g] = fwd_cell<T>(nb, c2, qc, fw, fe, fn, fs, u0.v[g], uw.v[g], ue.v[g], un.v[g], us.v[g],
+                                      vv.v[g]);
+            if (near) add_src<T, G>(vv, cell, sc);
 #pragma unroll
-        for (int g = 0; g < G; ++g) r.v[g] = u0.v[g] + vv.v[g];
+            for (int g = 0; g < G; ++g) r.v[g] = u0.v[g] + vv.v[g];
+        } else {
+            const T qc = Q[k];
+            const Vec<T, G> u0 = U[k], uw = U[k - 1], ue = U[k + 1], un = U[k - W], us = U[k + W];
+            if (damp) {
+                T nb, c2;
+                damp_inc<T>(D[x + 3] + D[W + z + 3], nb, c2);
+#pragma unroll
+                for (int g = 0; g < G; ++g)
+                    vv.v[g] = fwd_cell<T>(nb, c2, qc, fw, fe, fn, fs, u0.v[g], uw.v[g], ue.v[g], un.v[g], us.v[g],
+                                          vv.v[g]);
+            } else {
+#pragma unroll
+                for (int g = 0; g < G; ++g)
+                    vv.v[g] = fwd_cell_free<T>(qc, fw, fe, fn, fs, u0.v[g], uw.v[g], ue.v[g], un.v[g], us.v[g],
+                                               vv.v[g]);
+            }
+            if (near) add_src<T, G>(vv, cell, sc);
+#pragma unroll
+            for (int g = 0; g < G; ++g) r.v[g] = u0.v[g] + vv.v[g];
+        }
         return r;
     };
     auto lds_at = [&](int x, int z) { return (z + 3) * W + x + 3; };
