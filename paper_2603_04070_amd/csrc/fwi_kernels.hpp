@@ -597,6 +597,31 @@ __device__ __forceinline__ void faces(bool hw, bool he, bool hn, bool hs, T bc, 
     fs = hs ? hf * (bc + bs) : bc;
 }
 
+// The same face buoyancies from staged values hb = bt/2 that repeat the
+// nearest grid cell's beyond the grid edge: one addition per face, equal to
+// faces() bit for bit (halving is exact and commutes with the rounding of the
+// sum; a border face gives bt/2 + bt/2 = bt).
+template <typename T>
+__device__ __forceinline__ void faces_h(T bc, T bw, T be, T bn, T bs, T& fw, T& fe, T& fn, T& fs)
+{
+    fw = bc + bw;
+    fe = bc + be;
+    fn = bc + bn;
+    fs = bc + bs;
+}
+
+// (q, bt/2) of one staged cell (gx, gz): q in the grid (zero outside, where
+// no update reads it), bt/2 of the nearest grid cell, for faces_h.
+template <typename T>
+__device__ __forceinline__ void stage_coef(const T* cf, bool in, int gx, int gz, int nx, int nz, T& q, T& hb)
+{
+    const int cx = min(max(gx, 0), nx - 1), cz = min(max(gz, 0), nz - 1);
+    const uint32_t x = (uint32_t)(cz * nx + cx);
+    const T qv = ldg32(cf, 2 * x), bv = ldg32(cf, 2 * x + 1);
+    q = in ? qv : T(0);
+    hb = T(0.5) * bv;
+}
+
 // Plane of u^tau read by a forward-type step: zero for tau = 0; on
 // recompute, the checkpoint of segment j for tau = jK; else segment slot
 // (tau-1) mod K.
@@ -1067,9 +1092,7 @@ __device__ void tile_forward2(const Item<T, Acc>& it, const Step& st, int tile_x
         const bool in = c < L::N0 && gx >= 0 && gx < nx && gz >= 0 && gz < nz;
         const uint32_t x = in ? (uint32_t)(gz * nx + gx) : 0u;
         f0[i] = vkeep<T, G>(in, vload32<T, G>(cur, x));
-        const T q = ldg32(cf, 2 * x), bt = ldg32(cf, 2 * x + 1);
-        q0[i] = in ? q : T(0);
-        b0[i] = in ? bt : T(0);
+        stage_coef<T>(cf, in, gx, gz, nx, nz, q0[i], b0[i]);
     }
 #pragma unroll
     for (int k = 0; k < R; ++k) {
@@ -1101,8 +1124,7 @@ __device__ void tile_forward2(const Item<T, Acc>& it, const Step& st, int tile_x
         const int k = (ez + 1) * L::W0 + ex + 1;
         const uint32_t x = (uint32_t)(gz * nx + gx);
         T fw, fe, fn, fs, nb, c2;
-        faces<T>(gx > 0, gx < nx - 1, gz > 0, gz < nz - 1, B0[k], B0[k - 1],
-                 B0[k + 1], B0[k - L::W0], B0[k + L::W0], fw, fe, fn, fs);
+        faces_h<T>(B0[k], B0[k - 1], B0[k + 1], B0[k - L::W0], B0[k + L::W0], fw, fe, fn, fs);
         damp_inc<T>(D[ex + 1] + D[L::W0 + ez + 1], nb, c2);
         const T q = Q0[k];
         const Vec<T, G> u0 = U0[k], uw = U0[k - 1], ue = U0[k + 1], un = U0[k - L::W0], us = U0[k + L::W0];
@@ -1151,8 +1173,7 @@ __device__ void tile_forward2(const Item<T, Acc>& it, const Step& st, int tile_x
                 const int k0 = (ez + 2) * L::W0 + threadIdx.x + 2;
                 const uint32_t x = (uint32_t)(iz * nx + ix);
                 T fw, fe, fn, fs, nb, c2;
-                faces<T>(ix > 0, ix < nx - 1, iz > 0, iz < nz - 1, B0[k0], B0[k0 - 1],
-                         B0[k0 + 1], B0[k0 - L::W0], B0[k0 + L::W0], fw, fe, fn, fs);
+                faces_h<T>(B0[k0], B0[k0 - 1], B0[k0 + 1], B0[k0 - L::W0], B0[k0 + L::W0], fw, fe, fn, fs);
                 damp_inc<T>(exd + D[L::W0 + ez + 2], nb, c2);
                 const T q = Q0[k0];
                 const Vec<T, G> u0 = U1[k1], uw = U1[k1 - 1], ue = U1[k1 + 1], un = U1[k1 - L::W1],
@@ -1277,9 +1298,7 @@ __device__ void tile_forward3(const Item<T, Acc>& it, const Step& st, int tile_x
         const bool in = c < L::N3 && gx >= 0 && gx < nx && gz >= 0 && gz < nz;
         const uint32_t x = in ? (uint32_t)(gz * nx + gx) : 0u;
         f[i] = vkeep<T, G>(in, vload32<T, G>(cur, x));
-        const T qv = ldg32(cf, 2 * x), bv = ldg32(cf, 2 * x + 1);
-        q[i] = in ? qv : T(0);
-        b[i] = in ? bv : T(0);
+        stage_coef<T>(cf, in, gx, gz, nx, nz, q[i], b[i]);
     }
 #pragma unroll
     for (int k = 0; k < R; ++k) {
@@ -1317,8 +1336,7 @@ __device__ void tile_forward3(const Item<T, Acc>& it, const Step& st, int tile_x
         const int k = (z + 3) * W + x + 3;
         const int cell = gz * nx + gx;
         T fw, fe, fn, fs;
-        faces<T>(gx > 0, gx < nx - 1, gz > 0, gz < nz - 1, B[k], B[k - 1], B[k + 1], B[k - W], B[k + W],
-                 fw, fe, fn, fs);
+        faces_h<T>(B[k], B[k - 1], B[k + 1], B[k - W], B[k + W], fw, fe, fn, fs);
         Vec<T, G> r;
         if constexpr (DualOf<T>::is) {
             T nb, c2;
@@ -1482,9 +1500,7 @@ __device__ void tile_adjoint2(const Item<T, Acc>& it, const Step& st, int tile_x
         const bool in = c < L::N0 && ix0 >= 0 && ix0 < nx && iz0 >= 0 && iz0 < nz;
         const uint32_t x = in ? (uint32_t)(iz0 * nx + ix0) : 0u;
         f0[i] = vkeep<T, G>(in, vload32<T, G>(cur, x));
-        const T q = ldg32(cf, 2 * x), bt = ldg32(cf, 2 * x + 1);
-        q0[i] = in ? q : T(0);
-        b0[i] = in ? bt : T(0);
+        stage_coef<T>(cf, in, ix0, iz0, nx, nz, q0[i], b0[i]);
     }
 #pragma unroll
     for (int i = 0; i < L::P1; ++i) {
@@ -1533,8 +1549,7 @@ __device__ void tile_adjoint2(const Item<T, Acc>& it, const Step& st, int tile_x
     if (rin) {
         const int k = (rez + 1) * L::W0 + rex + 1;
         T fw, fe, fn, fs, a, b;
-        faces<T>(rx1 > 0, rx1 < nx - 1, rz1 > 0, rz1 < nz - 1, B0[k], B0[k - 1], B0[k + 1], B0[k - L::W0],
-                 B0[k + L::W0], fw, fe, fn, fs);
+        faces_h<T>(B0[k], B0[k - 1], B0[k + 1], B0[k - L::W0], B0[k + L::W0], fw, fe, fn, fs);
         damp_coeffs<T>(D[rex + 1] + D[L::W0 + rez + 1], a, b);
         const T qc = Q0[k];
         const Vec<T, G> l0 = L0[k], lw = L0[k - 1], le = L0[k + 1], ln = L0[k - L::W0], ls = L0[k + L::W0];
@@ -1557,7 +1572,7 @@ __device__ void tile_adjoint2(const Item<T, Acc>& it, const Step& st, int tile_x
             const int k0 = (ez + 2) * L::W0 + threadIdx.x + 2;
             const bool hn = iz > 0, hs = iz < nz - 1;
             T fw, fe, fn, fs, a, b;
-            faces<T>(hw, he, hn, hs, B0[k0], B0[k0 - 1], B0[k0 + 1], B0[k0 - L::W0], B0[k0 + L::W0], fw, fe, fn, fs);
+            faces_h<T>(B0[k0], B0[k0 - 1], B0[k0 + 1], B0[k0 - L::W0], B0[k0 + L::W0], fw, fe, fn, fs);
             damp_coeffs<T>(D[threadIdx.x + 2] + D[L::W0 + ez + 2], a, b);
             const T cn = hn ? hf : T(1), cs = hs ? hf : T(1);
             const T qc = Q0[k0];
@@ -1614,8 +1629,7 @@ __device__ void tile_adjoint2(const Item<T, Acc>& it, const Step& st, int tile_x
                 const uint32_t x = (uint32_t)(iz * nx + ix);
                 const bool hn = iz > 0, hs = iz < nz - 1;
                 T fw, fe, fn, fs, a, b;
-                faces<T>(hw, he, hn, hs, B0[k0], B0[k0 - 1], B0[k0 + 1],
-                         B0[k0 - L::W0], B0[k0 + L::W0], fw, fe, fn, fs);
+                faces_h<T>(B0[k0], B0[k0 - 1], B0[k0 + 1], B0[k0 - L::W0], B0[k0 + L::W0], fw, fe, fn, fs);
                 const T cn = hn ? hf : T(1), cs = hs ? hf : T(1);
                 damp_coeffs<T>(exd + D[L::W0 + ez + 2], a, b);
                 const T qc = Q0[k0];
