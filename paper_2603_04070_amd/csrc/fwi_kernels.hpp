@@ -1052,7 +1052,7 @@ __device__ void tile_forward2(const Item<T, Acc>& it, const Step& st, int tile_x
     const int nx = it.nx, nz = it.nz, n = st.n;
     Vec<T, G>* U0 = reinterpret_cast<Vec<T, G>*>(smem);                  // u^n, tile + 2
     T* Q0 = reinterpret_cast<T*>(U0 + L::N0);                            // q, tile + 2
-    T* B0 = Q0 + L::N0;                                                  // bt, tile + 2
+    T* B0 = Q0 + L::N0;                                                  // bt/2, tile + 2 (edge-replicated)
     Vec<T, G>* U1 = U0;                                                  // u^{n+1}, tile + 1, over u^n
     T* D = B0 + L::N0;                                                   // damping
     const T* cur = fwd_plane(it, st, n);
@@ -1079,7 +1079,7 @@ __device__ void tile_forward2(const Item<T, Acc>& it, const Step& st, int tile_x
     const T* exd_p = it.ex;
     const T* ezd_p = it.ez;
 
-    // one burst: u^n and (q, bt) on the tile grown by 2; v^n at this lane's
+    // one burst: u^n and (q, bt/2) on the tile grown by 2; v^n at this lane's
     // tile cells and ring cell; the damping profile.  Cells outside the grid
     // (or beyond the grown tile) load cell 0 and are replaced by zeros.
     Vec<T, G> f0[L::P0], vt[R], vr;
@@ -1253,7 +1253,7 @@ __device__ void tile_forward3(const Item<T, Acc>& it, const Step& st, int tile_x
     const int nx = it.nx, nz = it.nz, n = st.n;
     Vec<T, G>* U = reinterpret_cast<Vec<T, G>*>(smem);                   // u^n, then u^{n+1}, u^{n+2}
     T* Q = reinterpret_cast<T*>(U + L::N3);                              // q, tile + 3
-    T* B = Q + L::N3;                                                    // bt, tile + 3
+    T* B = Q + L::N3;                                                    // bt/2, tile + 3 (edge-replicated)
     T* D = B + L::N3;                                                    // damping
     const T* cur = fwd_plane(it, st, n);
     const T* vin = vel_in(it, st, n);
@@ -1286,7 +1286,7 @@ __device__ void tile_forward3(const Item<T, Acc>& it, const Step& st, int tile_x
     const bool in1 = tid < L::NR1 && x0 + r1x >= 0 && x0 + r1x < nx && z0 + r1z >= 0 && z0 + r1z < nz;
     const bool in2 = tid < L::NR2 && x0 + r2x >= 0 && x0 + r2x < nx && z0 + r2z >= 0 && z0 + r2z < nz;
 
-    // one burst: u^n and (q, bt) on the tile grown by 3; v^n at this lane's
+    // one burst: u^n and (q, bt/2) on the tile grown by 3; v^n at this lane's
     // cells; the damping profile
     Vec<T, G> f[L::P3], vt[R], v1, v2;
     T q[L::P3], b[L::P3];
@@ -1457,7 +1457,7 @@ __device__ void tile_adjoint2(const Item<T, Acc>& it, const Step& st, int tile_x
     // level, the values are w.
     Vec<T, G>* L0 = reinterpret_cast<Vec<T, G>*>(smem);                  // w^t, tile + 2
     T* Q0 = reinterpret_cast<T*>(L0 + L::N0);                            // q, tile + 2
-    T* B0 = Q0 + L::N0;                                                  // bt, tile + 2
+    T* B0 = Q0 + L::N0;                                                  // bt/2, tile + 2 (edge-replicated)
     // two tile + 1 planes without their first and last (corner) cells: X holds
     // u^{t-1} for the imaging of (lam^t, u^{t-1}), then w^{t-1}; Y holds u^{t-2}
     Vec<T, G>* X = reinterpret_cast<Vec<T, G>*>(B0 + L::N0) - 1;
@@ -1480,7 +1480,7 @@ __device__ void tile_adjoint2(const Item<T, Acc>& it, const Step& st, int tile_x
     Acc* accB = it.acc + ncell;
     const int ix = x0 + (int)threadIdx.x;
 
-    // one burst: lam^t and (q, bt) on the tile grown by 2; lam^{t+1}, u^{t-1},
+    // one burst: lam^t and (q, bt/2) on the tile grown by 2; lam^{t+1}, u^{t-1},
     // u^{t-2} on the tile grown by 1; the damping profile; this thread's
     // imaging accumulators
     Vec<T, G> f0[L::P0], ua[L::P1], ub[L::P1], pvt[R], pvr;
