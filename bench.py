@@ -176,6 +176,10 @@ def run_unfold(args):
     torch.manual_seed(0)
     model = DUFWI(grids, K=args.unfold_k, arch="small", hidden=32, physics_backprop=args.unfold_backprop).to(dev)
     progress("unfolded network built")
+    keys = ("recompute_updates", "waves", "launches", "max_ckpt", "steps_per_launch", "group")
+    progress(f"gradient plan {dict((k, model.plan.info[k]) for k in keys)}")
+    if model.hvp_plan is not None:
+        progress(f"hvp plan {dict((k, model.hvp_plan.info[k]) for k in keys)}")
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float32)).to(dev)
     c0 = torch.full((16, 512, 512), 1540.0, device=dev)
     rho = torch.stack([t(m.rho) for m in media])

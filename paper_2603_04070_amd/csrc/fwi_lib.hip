@@ -827,9 +827,14 @@ static fwi_status create_impl(fwi_plan* p, fwi_dtype dtype, const fwi_grid* grid
         // (MI355X, FP32, groups of 4, three forward steps per launch: 2.26 ps
         // per executed update and 10 us per launch reproduce both the
         // one-wave checkpointed and the 22-wave store-all timing of the
-        // 64-media benchmark workload; FP64 updates cost twice as much)
+        // 64-media benchmark workload; FP64 updates cost twice as much, and
+        // so does a Hessian-vector product's dual-number update against one
+        // of its real type: 5.76 s per product on the 16-media 512^2
+        // unfolded workload, every plane kept in 37 waves, is 4.2 ps per
+        // FP32 dual update once 10 us per launch is taken off)
         auto model_seconds = [&](const std::vector<Wave>& waves) {
-            const double t_update = 2.26e-12 * (dtype == FWI_F64 ? 2.0 : 1.0), t_launch = 10e-6;
+            const double t_update = 2.26e-12 * (dtype == FWI_F64 ? 2.0 : 1.0) * (p->hvp ? 2.0 : 1.0),
+                         t_launch = 10e-6;
             int S = p->S;
             for (auto& it : p->items)
                 if (S >= 2 && it.K < 4 && it.K < p->media[it.medium].g.nt) S = 1;
