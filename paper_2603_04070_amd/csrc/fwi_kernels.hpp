@@ -1320,13 +1320,8 @@ __device__ void tile_forward3(const Item<T, Acc>& it, const Step& st, int tile_x
     }
     if (tid < L::ND) D[tid] = dmp;
     // no absorbing layer within the tile grown by three: -beta = 1 and c2 = 0
-    // at every cell this launch updates (a wave-uniform branch below; dual
-    // fields keep the general update)
-    bool damp = true;
-    if constexpr (DualOf<T>::is)
-        __syncthreads();
-    else
-        damp = __syncthreads_or(tid < L::ND && dmp != T(0)) != 0;
+    // at every cell this launch updates (a wave-uniform branch below)
+    const bool damp = __syncthreads_or(tid < L::ND && !(dmp == T(0))) != 0;
 
     // one step at cell (x, z) of the grid (tile-relative) from the level in
     // U: v of the next level into vv (v of this level given there), u of the
@@ -1338,38 +1333,24 @@ __device__ void tile_forward3(const Item<T, Acc>& it, const Step& st, int tile_x
         T fw, fe, fn, fs;
         faces_h<T>(B[k], B[k - 1], B[k + 1], B[k - W], B[k + W], fw, fe, fn, fs);
         Vec<T, G> r;
-        if constexpr (DualOf<T>::is) {
+        const T qc = Q[k];
+        const Vec<T, G> u0 = U[k], uw = U[k - 1], ue = U[k + 1], un = U[k - W], us = U[k + W];
+        if (damp) {
             T nb, c2;
             damp_inc<T>(D[x + 3] + D[W + z + 3], nb, c2);
-            const T qc = Q[k];
-            const Vec<T, G> u0 = U[k], uw = U[k - 1], ue = U[k + 1], un = U[k - W], us = U[k + W];
 #pragma unroll
             for (int g = 0; g < G; ++g)
                 vv.v[g] = fwd_cell<T>(nb, c2, qc, fw, fe, fn, fs, u0.v[g], uw.v[g], ue.v[g], un.v[g], us.v[g],
                                       vv.v[g]);
-            if (near) add_src<T, G>(vv, cell, sc);
-#pragma unroll
-            for (int g = 0; g < G; ++g) r.v[g] = u0.v[g] + vv.v[g];
         } else {
-            const T qc = Q[k];
-            const Vec<T, G> u0 = U[k], uw = U[k - 1], ue = U[k + 1], un = U[k - W], us = U[k + W];
-            if (damp) {
-                T nb, c2;
-                damp_inc<T>(D[x + 3] + D[W + z + 3], nb, c2);
 #pragma unroll
-                for (int g = 0; g < G; ++g)
-                    vv.v[g] = fwd_cell<T>(nb, c2, qc, fw, fe, fn, fs, u0.v[g], uw.v[g], ue.v[g], un.v[g], us.v[g],
-                                          vv.v[g]);
-            } else {
-#pragma unroll
-                for (int g = 0; g < G; ++g)
-                    vv.v[g] = fwd_cell_free<T>(qc, fw, fe, fn, fs, u0.v[g], uw.v[g], ue.v[g], un.v[g], us.v[g],
-                                               vv.v[g]);
-            }
-            if (near) add_src<T, G>(vv, cell, sc);
-#pragma unroll
-            for (int g = 0; g < G; ++g) r.v[g] = u0.v[g] + vv.v[g];
+            for (int g = 0; g < G; ++g)
+                vv.v[g] = fwd_cell_free<T>(qc, fw, fe, fn, fs, u0.v[g], uw.v[g], ue.v[g], un.v[g], us.v[g],
+                                           vv.v[g]);
         }
+        if (near) add_src<T, G>(vv, cell, sc);
+#pragma unroll
+        for (int g = 0; g < G; ++g) r.v[g] = u0.v[g] + vv.v[g];
         return r;
     };
     auto lds_at = [&](int x, int z) { return (z + 3) * W + x + 3; };
